@@ -261,13 +261,11 @@ def leaf_knn(X: np.ndarray, perm: np.ndarray, leaf_off: np.ndarray, k: int):
     dist = np.full((n, k), np.inf, dtype=np.float64)
     for L in range(len(leaf_off) - 1):
         mem = np.asarray(perm[leaf_off[L]:leaf_off[L + 1]], dtype=np.int64)
-        if len(mem) == 0:
-            continue
         Y = X[mem].astype(np.float64)
-        D = ((Y[:, None, :] - Y[None, :, :]) ** 2).sum(-1)
         for a, i in enumerate(mem):
+            D = ((Y - Y[a]) ** 2).sum(1)
             others = np.delete(np.arange(len(mem)), a)
-            ids[i], dist[i] = _keep_k(mem[others].astype(np.uint32), D[a, others], k)
+            ids[i], dist[i] = _keep_k(mem[others].astype(np.uint32), D[others], k)
     return ids, dist
 
 

@@ -1,0 +1,364 @@
+// One level of a random division (Section 3.1; appendix median bipartition;
+// Section 3.4 principal direction): project every point of every internal
+// node, select each node's split key by a 3-pass radix select over the
+// ordered key bits, and stable-partition the node's segment of the
+// permutation.  A node's segment is always sorted by point id (children keep
+// their parent's order and the root is 0..n-1), so the (key, id) order of
+// the split is "key, then position in the segment".
+#include "knng_dev.h"
+
+namespace knng {
+
+namespace {
+
+constexpr int DIV_THREADS = 256;
+constexpr int HB[3] = {(int)HIST_B0, (int)HIST_B1, (int)HIST_B2};
+__constant__ int c_hist_base[3] = {0, (int)HIST_B0, (int)(HIST_B0 + HIST_B1)};
+
+// --------------------------------------------------------------- block scans
+__device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total) {
+  // 256 threads = 4 waves
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int s = sh[i];
+    base += (i < w) ? s : 0;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+// Walks the histograms of passes 0..npass-1 of segment `sl` and returns the
+// selected key prefix and the remaining rank (block-uniform result).
+__device__ void resolve(const uint32_t* __restrict__ hist, uint32_t sl, uint32_t left, int npass, uint32_t* prefix,
+                        uint32_t* rank, int* sh) {
+  uint32_t pre = 0, r = left;
+  for (int q = 0; q < npass; ++q) {
+    const uint32_t* h = hist + (size_t)sl * HIST_TOTAL + c_hist_base[q];
+    int nb = HB[q];
+    int per = nb / DIV_THREADS;            // 8 or 4 bins per thread
+    int b0 = threadIdx.x * per;
+    int mysum = 0;
+    for (int i = 0; i < per; ++i) mysum += (int)h[b0 + i];
+    int tot;
+    int before = block_excl_scan(mysum, sh, &tot);
+    // the thread whose bins straddle rank r finds the bin
+    if ((uint32_t)before <= r && r < (uint32_t)(before + mysum)) {
+      uint32_t c = before;
+      for (int i = 0; i < per; ++i) {
+        uint32_t hv = h[b0 + i];
+        if (r < c + hv) {
+          sh[8] = b0 + i;
+          sh[9] = (int)c;
+          break;
+        }
+        c += hv;
+      }
+    }
+    __syncthreads();
+    uint32_t bin = (uint32_t)sh[8], below = (uint32_t)sh[9];
+    __syncthreads();
+    int bits = (q == 2) ? 10 : 11;
+    pre = (pre << bits) | bin;
+    r -= below;
+  }
+  *prefix = pre;
+  *rank = r;
+}
+
+// --------------------------------------------------------------- direction
+__device__ void load_direction(const DivideLevelArgs& a, const SegDesc& sd, float* dir, bool first_item) {
+  for (int j = threadIdx.x; j < a.d; j += DIV_THREADS) {
+    float v;
+    if (a.dirs) v = a.dirs[(size_t)sd.dir_index * a.d + j];
+    else if (a.pca_iters > 0) v = a.pca_dirs[(size_t)sd.dir_index * a.d + j];
+    else v = rp_entry(a.seed, (uint32_t)a.t, sd.v, (uint32_t)j);
+    dir[j] = v;
+    if (a.dirs_out && first_item) a.dirs_out[(size_t)sd.dir_index * a.d + j] = v;
+  }
+  __syncthreads();
+}
+
+// key = a . x in float32, left to right, every product and sum rounded.
+__device__ __forceinline__ float dot_seq(const float* __restrict__ x, const float* __restrict__ a, int d) {
+#pragma clang fp contract(off)
+  float acc = 0.f;
+  const float4* xv = (const float4*)x;
+  for (int c = 0; c < (d >> 2); ++c) {
+    float4 u = xv[c];
+    float p0 = u.x * a[4 * c + 0];
+    acc = acc + p0;
+    float p1 = u.y * a[4 * c + 1];
+    acc = acc + p1;
+    float p2 = u.z * a[4 * c + 2];
+    acc = acc + p2;
+    float p3 = u.w * a[4 * c + 3];
+    acc = acc + p3;
+  }
+  return acc;
+}
+
+// --------------------------------------------------------------- kernels
+__global__ __launch_bounds__(DIV_THREADS) void k_proj_hist0(DivideLevelArgs a) {
+  extern __shared__ float dir[];
+  __shared__ uint32_t lh[HIST_B0];
+  const ItemDesc it = a.items[blockIdx.x];
+  const SegDesc sd = a.segs[it.seg];
+  for (int b = threadIdx.x; b < (int)HIST_B0; b += DIV_THREADS) lh[b] = 0;
+  load_direction(a, sd, dir, it.start == sd.off);
+  for (uint32_t i = threadIdx.x; i < it.len; i += DIV_THREADS) {
+    uint32_t pos = it.start + i;
+    uint32_t row = a.perm_in[pos];
+    float key = dot_seq(a.X + (size_t)row * a.d, dir, a.d);
+    uint32_t uk = ordered_key(key);
+    a.ukeys[pos] = uk;
+    atomicAdd(&lh[uk >> 21], 1u);
+  }
+  __syncthreads();
+  uint32_t* gh = a.hist + (size_t)it.seg * HIST_TOTAL;
+  for (int b = threadIdx.x; b < (int)HIST_B0; b += DIV_THREADS)
+    if (lh[b]) atomicAdd(&gh[b], lh[b]);
+}
+
+__global__ __launch_bounds__(DIV_THREADS) void k_hist_pass(DivideLevelArgs a, int pass) {
+  __shared__ uint32_t lh[HIST_B1];
+  __shared__ int sh[16];
+  const ItemDesc it = a.items[blockIdx.x];
+  const SegDesc sd = a.segs[it.seg];
+  uint32_t prefix, rank;
+  resolve(a.hist, it.seg, sd.left, pass, &prefix, &rank, sh);
+  int nb = HB[pass];
+  for (int b = threadIdx.x; b < nb; b += DIV_THREADS) lh[b] = 0;
+  __syncthreads();
+  int shift_pre = pass == 1 ? 21 : 10;
+  for (uint32_t i = threadIdx.x; i < it.len; i += DIV_THREADS) {
+    uint32_t uk = a.ukeys[it.start + i];
+    if ((uk >> shift_pre) == prefix) {
+      uint32_t dg = pass == 1 ? ((uk >> 10) & 0x7FF) : (uk & 0x3FF);
+      atomicAdd(&lh[dg], 1u);
+    }
+  }
+  __syncthreads();
+  uint32_t* gh = a.hist + (size_t)it.seg * HIST_TOTAL + c_hist_base[pass];
+  for (int b = threadIdx.x; b < nb; b += DIV_THREADS)
+    if (lh[b]) atomicAdd(&gh[b], lh[b]);
+}
+
+__global__ __launch_bounds__(DIV_THREADS) void k_part_count(DivideLevelArgs a) {
+  __shared__ int sh[16];
+  const ItemDesc it = a.items[blockIdx.x];
+  const SegDesc sd = a.segs[it.seg];
+  uint32_t pivot, need;
+  resolve(a.hist, it.seg, sd.left, 3, &pivot, &need, sh);
+  int nl = 0, ne = 0;
+  for (uint32_t i = threadIdx.x; i < it.len; i += DIV_THREADS) {
+    uint32_t uk = a.ukeys[it.start + i];
+    nl += uk < pivot;
+    ne += uk == pivot;
+  }
+  int tl, te;
+  block_excl_scan(nl, sh, &tl);
+  block_excl_scan(ne, sh, &te);
+  if (threadIdx.x == 0) {
+    a.chunk_cnt[2 * blockIdx.x] = (uint32_t)tl;
+    a.chunk_cnt[2 * blockIdx.x + 1] = (uint32_t)te;
+  }
+}
+
+__global__ __launch_bounds__(DIV_THREADS) void k_part_scatter(DivideLevelArgs a) {
+  __shared__ int sh[16];
+  const ItemDesc it = a.items[blockIdx.x];
+  if (it.seg == 0xFFFFFFFFu) {   // positions outside this level's internal nodes
+    for (uint32_t i = threadIdx.x; i < it.len; i += DIV_THREADS) a.perm_out[it.start + i] = a.perm_in[it.start + i];
+    return;
+  }
+  const SegDesc sd = a.segs[it.seg];
+  uint32_t pivot, need;
+  resolve(a.hist, it.seg, sd.left, 3, &pivot, &need, sh);
+  // counts of the segment's earlier chunks
+  int pl = 0, pe = 0;
+  for (uint32_t c = sd.first_item + threadIdx.x; c < blockIdx.x; c += DIV_THREADS) {
+    pl += (int)a.chunk_cnt[2 * c];
+    pe += (int)a.chunk_cnt[2 * c + 1];
+  }
+  int less_before, eq_before;
+  block_excl_scan(pl, sh, &less_before);
+  block_excl_scan(pe, sh, &eq_before);
+  uint32_t base_idx = it.start - sd.off;
+  for (uint32_t t0 = 0; t0 < it.len; t0 += DIV_THREADS) {
+    uint32_t i = t0 + threadIdx.x;
+    bool valid = i < it.len;
+    uint32_t uk = valid ? a.ukeys[it.start + i] : 0xFFFFFFFFu;
+    int isl = valid && uk < pivot, ise = valid && uk == pivot;
+    int tl, te;
+    int rl = block_excl_scan(isl, sh, &tl);
+    int re = block_excl_scan(ise, sh, &te);
+    if (valid) {
+      uint32_t nless = (uint32_t)(less_before + rl);   // less-than elements before this one
+      uint32_t neq = (uint32_t)(eq_before + re);        // equal elements before this one
+      uint32_t idx = base_idx + i;
+      uint32_t dest;
+      if (isl) {
+        dest = sd.off + nless + (neq < need ? neq : need);
+      } else if (ise && neq < need) {
+        dest = sd.off + nless + neq;
+      } else {
+        uint32_t lbefore = nless + (neq < need ? neq : need);
+        dest = sd.off + sd.left + (idx - lbefore);
+      }
+      a.perm_out[dest] = a.perm_in[it.start + i];
+    }
+    less_before += tl;
+    eq_before += te;
+  }
+}
+
+// Principal direction of a node sample by FP32 power iteration.
+__global__ __launch_bounds__(DIV_THREADS) void k_pca_dirs(DivideLevelArgs a) {
+  extern __shared__ float smem[];
+  float* mu = smem;               // d
+  float* v = mu + a.d;            // d
+  float* w = v + a.d;             // d
+  float* tt = w + a.d;            // 256
+  __shared__ uint32_t rows[256];
+  __shared__ float red[DIV_THREADS / 64];
+  __shared__ int redi[DIV_THREADS / 64];
+  const SegDesc sd = a.segs[blockIdx.x];
+  const int d = a.d;
+  uint32_t m = sd.m;
+  uint32_t s = m < 256 ? m : 256;
+  uint32_t wd = m / s;
+  if (wd < 1) wd = 1;
+  if (threadIdx.x < s) {
+    uint32_t pos = (uint32_t)(((uint64_t)threadIdx.x * m) / s) +
+                   (uint32_t)(rand64(a.seed, TAG_SAMPLE, (uint32_t)a.t, sd.v, threadIdx.x) % wd);
+    rows[threadIdx.x] = a.perm_in[sd.off + pos];
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < d; j += DIV_THREADS) {
+    float acc = 0.f;
+    for (uint32_t i = 0; i < s; ++i) acc += a.X[(size_t)rows[i] * d + j];
+    mu[j] = acc / (float)s;
+    v[j] = rp_entry(a.seed, (uint32_t)a.t, sd.v, (uint32_t)j);
+  }
+  __syncthreads();
+  auto block_sum = [&](float x) -> float {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    float r = 0.f;
+    for (int i = 0; i < DIV_THREADS / 64; ++i) r += red[i];
+    __syncthreads();
+    return r;
+  };
+  // normalise the start vector
+  float nn = 0.f;
+  for (int j = threadIdx.x; j < d; j += DIV_THREADS) nn += v[j] * v[j];
+  nn = block_sum(nn);
+  float inv = nn > 0.f ? 1.0f / sqrtf(nn) : 0.f;
+  for (int j = threadIdx.x; j < d; j += DIV_THREADS) v[j] *= inv;
+  __syncthreads();
+  for (int itr = 0; itr < a.pca_iters; ++itr) {
+    if (threadIdx.x < s) {
+      const float* x = a.X + (size_t)rows[threadIdx.x] * d;
+      float acc = 0.f;
+      for (int j = 0; j < d; ++j) acc += (x[j] - mu[j]) * v[j];
+      tt[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    float sq = 0.f;
+    for (int j = threadIdx.x; j < d; j += DIV_THREADS) {
+      float acc = 0.f;
+      for (uint32_t i = 0; i < s; ++i) acc += (a.X[(size_t)rows[i] * d + j] - mu[j]) * tt[i];
+      w[j] = acc;
+      sq += acc * acc;
+    }
+    sq = block_sum(sq);
+    if (sq > 0.f) {
+      float iv = 1.0f / sqrtf(sq);
+      for (int j = threadIdx.x; j < d; j += DIV_THREADS) v[j] = w[j] * iv;
+    }
+    __syncthreads();
+  }
+  // sign: the largest-magnitude entry positive, lowest index on ties
+  float best = -1.f;
+  int bj = 0x7FFFFFFF;
+  for (int j = threadIdx.x; j < d; j += DIV_THREADS) {
+    float av = fabsf(v[j]);
+    if (av > best) { best = av; bj = j; }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    float ob = __shfl_xor(best, o);
+    int oj = __shfl_xor(bj, o);
+    if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+  }
+  if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6] = best; redi[threadIdx.x >> 6] = bj; }
+  __syncthreads();
+  best = red[0]; bj = redi[0];
+  for (int i = 1; i < DIV_THREADS / 64; ++i)
+    if (red[i] > best || (red[i] == best && redi[i] < bj)) { best = red[i]; bj = redi[i]; }
+  float sg = v[bj] < 0.f ? -1.f : 1.f;
+  for (int j = threadIdx.x; j < d; j += DIV_THREADS) a.pca_dirs[(size_t)sd.dir_index * d + j] = sg * v[j];
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t value, size_t count) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = value;
+}
+
+__global__ void k_iota(uint32_t* p, uint32_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = (uint32_t)i;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, value, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota(uint32_t* p, uint32_t n, hipStream_t s) {
+  size_t blocks = ((size_t)n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_iota, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_fill_u32(a.hist, 0u, (size_t)a.n_segs * HIST_TOTAL, s)) != hipSuccess) return e;
+  if (a.pca_iters > 0 && !a.dirs) {
+    size_t shm = (size_t)(3 * a.d + 256) * sizeof(float);
+    hipLaunchKernelGGL(k_pca_dirs, dim3(a.n_segs), dim3(DIV_THREADS), shm, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_proj_hist0, dim3(a.n_split), dim3(DIV_THREADS), (size_t)a.d * sizeof(float), s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_hist_pass, dim3(a.n_split), dim3(DIV_THREADS), 0, s, a, 1);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_hist_pass, dim3(a.n_split), dim3(DIV_THREADS), 0, s, a, 2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_part_count, dim3(a.n_split), dim3(DIV_THREADS), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_part_scatter, dim3(a.n_items), dim3(DIV_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace knng

@@ -1,0 +1,360 @@
+// Combination of base graphs (Section 3.1) and neighbourhood propagation
+// rounds (Section 3.2, first-order form of Theorem 1, with the pairwise
+// updating of Section 3.4).  All kernels work one wave per point and keep
+// candidate sets in registers, sorted with wave-wide bitonic networks; they
+// are bound by the gathers of neighbour lists and candidate rows.
+#include "knng_dev.h"
+
+namespace knng {
+
+namespace {
+
+// ---------------------------------------------------------------- merge
+// Row p: the union of n_lists lists of k (distance, id) entries, duplicates
+// dropped, first k by (distance, id).  The same pair always carries the same
+// FP32 distance (one canonical distance routine), so duplicates sort next to
+// each other.
+template <int R>
+__global__ __launch_bounds__(256) void k_merge(int64_t n, int k, int n_lists, const uint32_t* __restrict__ ids_in,
+                                                const float* __restrict__ dist_in, uint32_t* __restrict__ ids_out,
+                                                float* __restrict__ dist_out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (p >= n) return;
+  const int tot = n_lists * k;
+  const size_t nk = (size_t)n * k;
+  uint64_t v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int e = r * 64 + lane;
+    uint64_t key = ~0ull;
+    if (e < tot) {
+      int li = e / k, j = e % k;
+      size_t idx = (size_t)li * nk + (size_t)p * k + j;
+      key = pack_did(dist_in[idx], ids_in[idx]);
+    }
+    v[r] = key;
+  }
+  wave_bitonic<R, 64 * R, uint64_t>(v, lane);
+  int base = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    uint64_t pv = prev_elem<R>(v, r, lane, ~0ull);
+    bool uniq = v[r] != ~0ull && key_id(pv) != key_id(v[r]);
+    int cnt;
+    int slot = base + wave_prefix_count(uniq, lane, &cnt);
+    if (uniq && slot < k) {
+      ids_out[(size_t)p * k + slot] = key_id(v[r]);
+      dist_out[(size_t)p * k + slot] = key_dist(v[r]);
+    }
+    base += cnt;
+  }
+  // pad
+  for (int s = base + lane; s < k; s += 64) {
+    ids_out[(size_t)p * k + s] = KNNG_NONE;
+    dist_out[(size_t)p * k + s] = __int_as_float(0x7F800000);
+  }
+}
+
+// ---------------------------------------------------------------- propagation, forward part
+// Wave per point p:
+//   1. C_p = ids of N(q) for q in N(p), sorted, duplicates, p and N(p) dropped;
+//   2. score every candidate with the canonical distance (16 lanes each);
+//   3. first k by (distance, id) of N(p) and C_p -> forward list;
+//   4. pairwise: propose p to every scored o when (D, p) beats o's frozen
+//      k-th entry (anything else could never enter o's list).
+template <int R1, int R2, int NCH>
+__global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
+  __shared__ uint32_t cand_s[4][64 * R1];
+  __shared__ float cd_s[4][64 * R1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t p = (int64_t)blockIdx.x * 4 + w;
+  if (p >= a.n) return;
+  const int k = a.k, d = a.d;
+  uint32_t nb = lane < k ? a.ids_in[(size_t)p * k + lane] : KNNG_NONE;
+  float nbd = lane < k ? a.dist_in[(size_t)p * k + lane] : __int_as_float(0x7F800000);
+  // 1. gather neighbours' lists
+  uint32_t c[R1];
+#pragma unroll
+  for (int r = 0; r < R1; ++r) {
+    int e = r * 64 + lane;
+    uint32_t o = KNNG_NONE;
+    int qi = e / k;
+    uint32_t q = __shfl(nb, qi < 64 ? qi : 0);
+    if (e < k * k && q != KNNG_NONE) o = a.ids_in[(size_t)q * k + (e % k)];
+    c[r] = o;
+  }
+  wave_bitonic<R1, 64 * R1, uint32_t>(c, lane);
+  int U = 0;
+#pragma unroll
+  for (int r = 0; r < R1; ++r) {
+    uint32_t pv = prev_elem<R1>(c, r, lane, KNNG_NONE);
+    uint32_t o = c[r];
+    bool u = o != KNNG_NONE && o != (uint32_t)p && o != pv;
+    // drop members of N(p); every lane runs every shuffle (a shuffle whose
+    // source lane is inactive does not deliver that lane's value)
+    for (int j = 0; j < k; ++j) {
+      uint32_t nj = (uint32_t)__shfl(nb, j);
+      u = u & (o != nj);
+    }
+    int cnt;
+    int slot = U + wave_prefix_count(u, lane, &cnt);
+    if (u) cand_s[w][slot] = o;
+    U += cnt;
+  }
+  wave_sync();
+  // 2. score: lane group g takes candidates g, g+4, ...; p's row in registers
+  //    (NCH float4 chunks per lane; NCH == 0 reads it from memory each time)
+  const int g = lane >> 4, gl = lane & 15;
+  const float* xp = a.X + (size_t)p * d;
+  if constexpr (NCH > 0) {
+    float4 xr[NCH];
+#pragma unroll
+    for (int i = 0; i < NCH; ++i) {
+      int cc = gl + 16 * i;
+      xr[i] = (cc < (d >> 2)) ? ((const float4*)xp)[cc] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    for (int base = 0; base < U; base += 4) {
+      int ci = base + g;
+      uint32_t o = ci < U ? cand_s[w][ci] : (uint32_t)p;
+      float dd = dist2_g16_reg<NCH>(xr, a.X + (size_t)o * d, d, gl);
+      if (gl == 0 && ci < U) cd_s[w][ci] = dd;
+    }
+  } else {
+    for (int base = 0; base < U; base += 4) {
+      int ci = base + g;
+      uint32_t o = ci < U ? cand_s[w][ci] : (uint32_t)p;
+      float dd = dist2_g16(xp, a.X + (size_t)o * d, d, gl);
+      if (gl == 0 && ci < U) cd_s[w][ci] = dd;
+    }
+  }
+  wave_sync();
+  if (lane == 0) atomicAdd(&a.diag->prop_candidates[blockIdx.x & (DIAG_SLOTS - 1)], (unsigned long long)U);
+  // 3. first k of N(p) and C_p
+  const uint64_t nbkey = lane < k ? pack_did(nbd, nb) : ~0ull;
+  uint64_t v[R2];
+#pragma unroll
+  for (int r = 0; r < R2; ++r) {
+    int e = r * 64 + lane;
+    uint64_t key = ~0ull;
+    if (e < k) key = nbkey;                       // e == lane here
+    else if (e - k < U) key = pack_did(cd_s[w][e - k], cand_s[w][e - k]);
+    v[r] = key;
+  }
+  wave_bitonic<R2, 64 * R2, uint64_t>(v, lane);
+  uint32_t* oi = a.pairwise ? a.fwd_ids : a.ids_out;
+  float* od = a.pairwise ? a.fwd_dist : a.dist_out;
+  if (lane < k) {
+    oi[(size_t)p * k + lane] = key_id(v[0]);
+    od[(size_t)p * k + lane] = key_dist(v[0]);
+  }
+  if (!a.pairwise) return;
+  // 4. reverse proposals into p's own k*k slots
+  uint32_t* slots = a.prop_buf + (size_t)p * k * k * 2;
+  int np = 0;
+  for (int base = 0; base < U; base += 64) {
+    int ci = base + lane;
+    bool ok = false;
+    uint32_t o = 0;
+    float dd = 0.f;
+    if (ci < U) {
+      o = cand_s[w][ci];
+      dd = cd_s[w][ci];
+      uint32_t kid = a.ids_in[(size_t)o * k + k - 1];
+      float kd = a.dist_in[(size_t)o * k + k - 1];
+      ok = pack_did(dd, (uint32_t)p) < pack_did(kd, kid);
+    }
+    int tot;
+    int pre = np + wave_prefix_count(ok, lane, &tot);
+    if (ok) {
+      slots[2 * pre] = o;
+      slots[2 * pre + 1] = __float_as_uint(dd);
+      atomicAdd(&a.cnt[o], 1u);
+    }
+    np += tot;
+  }
+  if (lane == 0) {
+    a.prop_n[p] = (uint32_t)np;
+    atomicAdd(&a.diag->prop_proposals[blockIdx.x & (DIAG_SLOTS - 1)], (unsigned long long)np);
+  }
+}
+
+// ---------------------------------------------------------------- scan (exclusive, n+1 entries)
+__global__ __launch_bounds__(1024) void k_scan_blocks(const uint32_t* in, uint32_t* out, uint32_t* bsum, int64_t cnt) {
+  __shared__ uint32_t ws[16];
+  int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  uint32_t v = i < cnt ? in[i] : 0u;
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) ws[w] = x;
+  __syncthreads();
+  uint32_t base = 0;
+  for (int j = 0; j < w; ++j) base += ws[j];
+  if (i < cnt) out[i] = base + x - v;
+  if (threadIdx.x == 1023) bsum[blockIdx.x] = base + x;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t* bsum, int nb) {
+  // single block: exclusive scan of nb block sums in place (nb <= 1024 * 16)
+  __shared__ uint32_t part[1024];
+  int per = (nb + 1023) / 1024;
+  int b0 = threadIdx.x * per;
+  uint32_t s = 0;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) s += bsum[b0 + i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    uint32_t y = threadIdx.x >= o ? part[threadIdx.x - o] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += y;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - s;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) {
+      uint32_t t = bsum[b0 + i];
+      bsum[b0 + i] = run;
+      run += t;
+    }
+}
+
+__global__ void k_scan_add(uint32_t* out, const uint32_t* bsum, int64_t cnt) {
+  int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  if (i < cnt) out[i] += bsum[blockIdx.x];
+}
+
+// Proposals into per-destination buckets; leaves cnt[] at zero again.
+__global__ __launch_bounds__(256) void k_prop_scatter(PropArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (p >= a.n) return;
+  const uint32_t np = a.prop_n[p];
+  const uint32_t* slots = a.prop_buf + (size_t)p * a.k * a.k * 2;
+  for (uint32_t j = lane; j < np; j += 64) {
+    uint32_t dst = slots[2 * j];
+    uint32_t pos = a.offs[dst] + atomicSub(&a.cnt[dst], 1u) - 1u;
+    a.bucket[2 * pos] = (uint32_t)p;
+    a.bucket[2 * pos + 1] = slots[2 * j + 1];
+  }
+}
+
+// Row p: first k by (distance, id) of its forward list and its bucket.
+template <int R>
+__global__ __launch_bounds__(256) void k_prop_final(PropArgs a) {
+  __shared__ uint64_t kept[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t p = (int64_t)blockIdx.x * 4 + w;
+  if (p >= a.n) return;
+  const int k = a.k;
+  uint64_t keep = lane < k ? pack_did(a.fwd_dist[(size_t)p * k + lane], a.fwd_ids[(size_t)p * k + lane]) : ~0ull;
+  const uint32_t b0 = a.offs[p], b1 = a.offs[p + 1];
+  const uint32_t chunk = 64 * (R - 1);   // register 0 carries the kept list
+  uint32_t pos = b0;
+  do {
+    uint64_t v[R];
+    v[0] = keep;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      uint32_t j = pos + (uint32_t)((r - 1) * 64 + lane);
+      v[r] = j < b1 ? pack_did(__uint_as_float(a.bucket[2 * j + 1]), a.bucket[2 * j]) : ~0ull;
+    }
+    pos += chunk;
+    wave_bitonic<R, 64 * R, uint64_t>(v, lane);
+    // drop adjacent duplicates (same id carries the same distance) and keep the first k
+    kept[w][lane] = ~0ull;
+    wave_sync();
+    int base = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      uint64_t pv = prev_elem<R>(v, r, lane, ~0ull);
+      bool uniq = v[r] != ~0ull && key_id(pv) != key_id(v[r]);
+      int cnt;
+      int slot = base + wave_prefix_count(uniq, lane, &cnt);
+      if (uniq && slot < k) kept[w][slot] = v[r];
+      base += cnt;
+    }
+    wave_sync();
+    keep = kept[w][lane];
+    wave_sync();
+  } while (pos < b1);
+  if (lane < k) {
+    a.ids_out[(size_t)p * k + lane] = key_id(keep);
+    a.dist_out[(size_t)p * k + lane] = key_dist(keep);
+  }
+}
+
+template <int R>
+hipError_t launch_merge_r(int64_t n, int k, int n_lists, const uint32_t* ids_in, const float* dist_in,
+                          uint32_t* ids_out, float* dist_out, hipStream_t s) {
+  unsigned blocks = (unsigned)((n + 3) / 4);
+  hipLaunchKernelGGL(k_merge<R>, dim3(blocks), dim3(256), 0, s, n, k, n_lists, ids_in, dist_in, ids_out, dist_out);
+  return hipGetLastError();
+}
+
+template <int R1, int R2, int NCH>
+hipError_t launch_fwd(const PropArgs& a, hipStream_t s) {
+  unsigned blocks = (unsigned)((a.n + 3) / 4);
+  hipLaunchKernelGGL((k_prop_forward<R1, R2, NCH>), dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int R1, int R2>
+hipError_t launch_fwd_d(const PropArgs& a, hipStream_t s) {
+  int nc = a.d / 4;   // float4 chunks; lane owns ceil(nc/16)
+  if (nc <= 16) return launch_fwd<R1, R2, 1>(a, s);
+  if (nc <= 32) return launch_fwd<R1, R2, 2>(a, s);
+  if (nc <= 64) return launch_fwd<R1, R2, 4>(a, s);
+  if (nc <= 128) return launch_fwd<R1, R2, 8>(a, s);
+  if (nc <= 256) return launch_fwd<R1, R2, 16>(a, s);
+  return launch_fwd<R1, R2, 0>(a, s);
+}
+
+}  // namespace
+
+hipError_t launch_merge(int64_t n, int k, int n_lists, const uint32_t* ids_in, const float* dist_in,
+                        uint32_t* ids_out, float* dist_out, hipStream_t s) {
+  int tot = n_lists * k;
+  if (tot <= 64) return launch_merge_r<1>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s);
+  if (tot <= 128) return launch_merge_r<2>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s);
+  if (tot <= 256) return launch_merge_r<4>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s);
+  if (tot <= 512) return launch_merge_r<8>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s);
+  if (tot <= 1024) return launch_merge_r<16>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_propagate_round(const PropArgs& a, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_fill_u32((uint32_t*)a.diag->prop_candidates, 0u, 4 * DIAG_SLOTS, s)) != hipSuccess) return e;
+  if (a.pairwise) {
+    if ((e = launch_fill_u32(a.cnt, 0u, (size_t)a.n + 1, s)) != hipSuccess) return e;
+  }
+  int kk = a.k * a.k, kt = a.k * a.k + a.k;
+  if (kk <= 64 && kt <= 128) e = launch_fwd_d<1, 2>(a, s);
+  else if (kk <= 128 && kt <= 256) e = launch_fwd_d<2, 4>(a, s);
+  else if (kk <= 256 && kt <= 512) e = launch_fwd_d<4, 8>(a, s);
+  else if (kk <= 512 && kt <= 1024) e = launch_fwd_d<8, 16>(a, s);
+  else if (kk <= 1024 && kt <= 1024) e = launch_fwd_d<16, 16>(a, s);
+  else return hipErrorInvalidValue;
+  if (e != hipSuccess) return e;
+  if (!a.pairwise) return hipSuccess;
+  int64_t cnt = a.n + 1;
+  unsigned nb = (unsigned)((cnt + 1023) / 1024);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, a.cnt, a.offs, a.block_sums, cnt);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, a.block_sums, (int)nb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(1024), 0, s, a.offs, a.block_sums, cnt);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  unsigned blocks = (unsigned)((a.n + 3) / 4);
+  hipLaunchKernelGGL(k_prop_scatter, dim3(blocks), dim3(256), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (a.k <= 64) hipLaunchKernelGGL(k_prop_final<4>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace knng

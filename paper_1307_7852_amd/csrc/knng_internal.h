@@ -1,0 +1,150 @@
+// Internal declarations shared by the host API and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <vector>
+
+#include "../../include/knng.h"
+
+namespace knng {
+
+// ------------------------------------------------------------------ RNG
+// Counter-based generator: the SplitMix64 finaliser (Steele, Lea & Flood,
+// OOPSLA 2014) applied to the seed xor a mixed counter.  Counter fields:
+// tag (4 bits) | division t (12) | heap node id v (32) | index j (16).
+enum : uint32_t { TAG_DIR = 1, TAG_SPLIT = 2, TAG_SAMPLE = 3 };
+
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return z;
+}
+
+__host__ __device__ inline uint64_t rand64(uint64_t seed, uint32_t tag, uint32_t t, uint32_t v, uint32_t j) {
+  uint64_t ctr = ((uint64_t)tag << 60) | ((uint64_t)(t & 0xFFF) << 48) | ((uint64_t)v << 16) | (uint64_t)(j & 0xFFFF);
+  return mix64(seed ^ mix64(ctr));
+}
+
+// Random-projection entry: sum of the draw's four low bytes minus 510
+// (Irwin-Hall(4) stand-in for a Gaussian entry; exact small integer).
+__host__ __device__ inline float rp_entry(uint64_t seed, uint32_t t, uint32_t v, uint32_t j) {
+  uint64_t r = rand64(seed, TAG_DIR, t, v, j);
+  int s = (int)(r & 0xFF) + (int)((r >> 8) & 0xFF) + (int)((r >> 16) & 0xFF) + (int)((r >> 24) & 0xFF);
+  return (float)(s - 510);
+}
+
+// ------------------------------------------------------------------ tree plan
+struct SegDesc {          // one internal node of one level
+  uint32_t off, m, left, v;
+  uint32_t first_item;    // index of the node's first split item in the level's item list
+  uint32_t n_items;
+  uint32_t dir_index;     // index of the node among all internal nodes (level order)
+  uint32_t pad;
+};
+struct ItemDesc {         // a chunk of positions handled by one workgroup
+  uint32_t seg;           // level-local segment index (split items) or 0xFFFFFFFF (copy)
+  uint32_t start;         // first position
+  uint32_t len;
+  uint32_t pad;
+};
+struct LevelPlan {
+  uint32_t seg_begin, n_segs;      // into Plan::segs
+  uint32_t item_begin, n_split, n_items;  // into Plan::items (split items first, then copies)
+  uint32_t max_seg;
+};
+struct Plan {
+  int64_t n = 0;
+  int depth = 0;
+  std::vector<SegDesc> segs;
+  std::vector<ItemDesc> items;
+  std::vector<LevelPlan> levels;
+  std::vector<int64_t> leaf_off;
+  int64_t n_internal() const { return (int64_t)segs.size(); }
+  int64_t n_leaves() const { return (int64_t)leaf_off.size() - 1; }
+  uint32_t max_level_segs() const;
+  uint32_t max_level_items() const;
+};
+
+constexpr uint32_t DIV_CHUNK = 2048;      // positions per divide work item
+constexpr uint32_t HIST_B0 = 2048, HIST_B1 = 2048, HIST_B2 = 1024;   // 11 + 11 + 10 key bits
+constexpr uint32_t HIST_TOTAL = HIST_B0 + HIST_B1 + HIST_B2;
+
+int64_t leaf_cap(const knng_params& p, int t);
+int plan_tree(const knng_params& p, int t, Plan& out);   // returns knng_status
+
+// ------------------------------------------------------------------ workspace
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  }
+};
+
+// Device diagnostics block (start of every workspace).
+// Counters that many blocks bump are spread over DIAG_SLOTS addresses.
+constexpr int DIAG_SLOTS = 64;
+struct DiagDev {
+  unsigned long long leaf_fallback;    // rows redone exactly (cumulative)
+  unsigned long long leaf_rows;        // rows processed (cumulative)
+  unsigned long long fallback_count;   // entries in the current leaf fallback list
+  unsigned long long pad;
+  unsigned long long prop_candidates[DIAG_SLOTS];   // last round: sum of |C_p|
+  unsigned long long prop_proposals[DIAG_SLOTS];    // last round: proposals kept
+};
+
+// ------------------------------------------------------------------ launchers
+// Each returns hipSuccess or the first HIP error; they only enqueue.
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
+hipError_t launch_iota(uint32_t* p, uint32_t n, hipStream_t s);
+
+struct DivideLevelArgs {
+  const float* X; int d; uint64_t seed; int t;
+  const uint32_t* perm_in; uint32_t* perm_out;
+  uint32_t* ukeys;
+  const SegDesc* segs;       // level's segments (device)
+  const ItemDesc* items;     // level's items (device)
+  uint32_t n_segs, n_split, n_items;
+  uint32_t* hist;            // n_segs x HIST_TOTAL
+  uint32_t* chunk_cnt;       // n_split x 2
+  const float* dirs;         // nullable: n_internal x d (override or computed)
+  float* dirs_out;           // nullable
+  int pca_iters;             // > 0: compute principal directions into pca_dirs
+  float* pca_dirs;           // n_internal x d scratch when PCA
+};
+hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s);
+
+struct LeafArgs {
+  const float* X; int64_t n; int d; int k; int kp; int precision;
+  const uint32_t* perm; const int64_t* leaf_off; int64_t n_leaves;
+  uint32_t* ids; float* dist;
+  uint32_t* fallback;        // list of (leaf, position) pairs, capacity n
+  DiagDev* diag;
+};
+hipError_t launch_leaf(const LeafArgs& a, hipStream_t s);
+
+hipError_t launch_merge(int64_t n, int k, int n_lists, const uint32_t* ids_in, const float* dist_in,
+                        uint32_t* ids_out, float* dist_out, hipStream_t s);
+
+struct PropArgs {
+  const float* X; int64_t n; int d; int k; int pairwise;
+  const uint32_t* ids_in; const float* dist_in;
+  uint32_t* ids_out; float* dist_out;
+  uint32_t* fwd_ids; float* fwd_dist;     // forward results (pairwise)
+  uint32_t* prop_buf;                     // per point p: k*k slots of (dst, dist)
+  uint32_t* prop_n;                       // per point: proposals written
+  uint32_t* cnt;                          // n + 1
+  uint32_t* offs;                         // n + 1
+  uint32_t* block_sums;                   // scan scratch
+  uint32_t* bucket;                       // (src, dist) pairs grouped by dst
+  DiagDev* diag;
+};
+hipError_t launch_propagate_round(const PropArgs& a, hipStream_t s);
+
+}  // namespace knng

@@ -1,0 +1,452 @@
+// Exact k-NN inside every leaf subset (Section 3.1's brute-force subgraph).
+//
+// One workgroup (4 waves) per leaf.  Each wave owns 32 queries at a time and
+// streams the leaf's members through MFMA in tiles of 32 candidates:
+//   G[c][q] = x_c . x_q         (v_mfma_f32_32x32x2_f32, or the BF16 form
+//                                v_mfma_f32_32x32x16_bf16 on leaf-centred data)
+//   s[c][q] = |x_c|^2 - 2 G     (the query's own norm is constant per row)
+// A lane holds one query and 16 of every tile's 32 candidates; it keeps its
+// best KP candidates in a sorted register list fed through a small LDS
+// queue, so lanes with nothing to insert do not stall the others.  The two
+// lanes sharing a query exchange thresholds after every tile and merge their
+// lists at the end.  The KP survivors are re-scored with the canonical FP32
+// distance, sorted by (distance, id), and the first k written.  A row whose
+// k-th exact distance is not safely below every rejected candidate's lower
+// bound (from the Gram's error bound) is redone exactly by k_leaf_exact.
+#include "knng_dev.h"
+
+namespace knng {
+
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int LEAF_THREADS = 256;
+constexpr int QPW = 32;            // queries per wave
+constexpr int QPB = 128;           // queries per block pass
+constexpr int TILE = 32;           // candidates per tile
+constexpr int QUEUE = 16;          // per-lane queue slots (one tile's share)
+
+template <int KP>
+__device__ __forceinline__ void list_insert(float (&v)[KP], int (&p)[KP], float x, int px) {
+#pragma unroll
+  for (int s = KP - 1; s > 0; --s) {
+    bool sh = x < v[s - 1];
+    bool tk = x < v[s];
+    float nv = sh ? v[s - 1] : x;
+    int np = sh ? p[s - 1] : px;
+    v[s] = tk ? nv : v[s];
+    p[s] = tk ? np : p[s];
+  }
+  bool t0 = x < v[0];
+  v[0] = t0 ? x : v[0];
+  p[0] = t0 ? px : p[0];
+}
+
+__device__ __forceinline__ float4 ld4(const float* p) { return *(const float4*)p; }
+
+constexpr int MU_MAX = 2048;        // BF16 path: d <= 2048
+
+// Per-wave scratch, reused by phase: the tile loop's queues (64 lanes x
+// QUEUE float2), then the two half-lists of every query (2 x QPW x KP
+// float2), then positions / approximate values / exact distances
+// (3 x QPW x KP words).
+template <int KP>
+constexpr int scratch_bytes() { return (64 * QUEUE * 8 > QPW * KP * 16) ? 64 * QUEUE * 8 : QPW * KP * 16; }
+
+template <int KP, bool BF16>
+struct LeafShared {
+  uint32_t ids[KNNG_MAX_LEAF];
+  float nrm[KNNG_MAX_LEAF];
+  float tnorm[4][TILE];
+  float mu[BF16 ? MU_MAX : 1];
+  float red[8];
+  int flag;
+  alignas(16) unsigned char scratch[4][scratch_bytes<KP>()];
+};
+
+// Fragments: lane (h = lane/32, r = lane%32) owns features [h*HALF, h*HALF+HALF)
+// of each KC-wide chunk; MFMA step s uses feature h*HALF + s (FP32) or
+// h*HALF + 8 s .. +7 (BF16).  A and B use the same mapping, so the
+// contraction covers every feature exactly once.
+template <int KC, bool BF16>
+struct Frag {
+  static constexpr int HALF = KC / 2;
+  static constexpr int N4 = HALF / 4;
+  float4 f[N4];
+  __device__ __forceinline__ void load(const float* __restrict__ row, int kc, int d, int h, const float* mu, bool ok) {
+#pragma unroll
+    for (int i = 0; i < N4; ++i) {
+      int c = kc + h * HALF + 4 * i;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (ok && c < d) {
+        v = ld4(row + c);
+        if (BF16) {
+          v.x -= mu[c]; v.y -= mu[c + 1]; v.z -= mu[c + 2]; v.w -= mu[c + 3];
+        }
+      }
+      f[i] = v;
+    }
+  }
+};
+
+template <int KC, bool BF16>
+__device__ __forceinline__ void gram_chunk(const Frag<KC, BF16>& a, const Frag<KC, BF16>& b, f32x16& acc0, f32x16& acc1) {
+  if constexpr (!BF16) {
+#pragma unroll
+    for (int i = 0; i < Frag<KC, BF16>::N4; ++i) {
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.f[i].x, b.f[i].x, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.f[i].y, b.f[i].y, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.f[i].z, b.f[i].z, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.f[i].w, b.f[i].w, acc1, 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Frag<KC, BF16>::N4; i += 2) {
+      bf16x8 av, bv;
+      av[0] = (__bf16)a.f[i].x; av[1] = (__bf16)a.f[i].y; av[2] = (__bf16)a.f[i].z; av[3] = (__bf16)a.f[i].w;
+      av[4] = (__bf16)a.f[i + 1].x; av[5] = (__bf16)a.f[i + 1].y; av[6] = (__bf16)a.f[i + 1].z; av[7] = (__bf16)a.f[i + 1].w;
+      bv[0] = (__bf16)b.f[i].x; bv[1] = (__bf16)b.f[i].y; bv[2] = (__bf16)b.f[i].z; bv[3] = (__bf16)b.f[i].w;
+      bv[4] = (__bf16)b.f[i + 1].x; bv[5] = (__bf16)b.f[i + 1].y; bv[6] = (__bf16)b.f[i + 1].z; bv[7] = (__bf16)b.f[i + 1].w;
+      if ((i / 2) % 2 == 0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc0, 0, 0, 0);
+      else acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc1, 0, 0, 0);
+    }
+  }
+}
+
+__device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; }
+
+template <int KC, int KP, bool BF16>
+__global__ __launch_bounds__(LEAF_THREADS) void k_leaf(LeafArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  LeafShared<KP, BF16>& S = *reinterpret_cast<LeafShared<KP, BF16>*>(smem_raw);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, h = lane >> 5, r32 = lane & 31;
+  const int d = a.d, k = a.k;
+  const int64_t L = blockIdx.x;
+  const int64_t off = a.leaf_off[L];
+  const int m = (int)(a.leaf_off[L + 1] - off);
+  if (m <= 0) return;
+  if (tid == 0) atomicAdd(&a.diag->leaf_rows, (unsigned long long)m);
+  if (m > KNNG_MAX_LEAF) {   // every row goes to the exact kernel
+    for (int i = tid; i < m; i += LEAF_THREADS) {
+      unsigned long long slot = atomicAdd(&a.diag->fallback_count, 1ull);
+      atomicAdd(&a.diag->leaf_fallback, 1ull);
+      if (slot < (unsigned long long)a.n) {   // capacity n: leaves partition the points
+        a.fallback[2 * slot] = (uint32_t)L;
+        a.fallback[2 * slot + 1] = (uint32_t)i;
+      }
+    }
+    return;
+  }
+  for (int i = tid; i < m; i += LEAF_THREADS) S.ids[i] = a.perm[off + i];
+  if (tid == 0) S.flag = 1;
+  __syncthreads();
+  // ---- prologue: leaf mean (BF16), member norms, exactness flag, norm bounds
+  if constexpr (BF16) {
+    for (int j = tid; j < d; j += LEAF_THREADS) {
+      float acc = 0.f;
+      for (int i = 0; i < m; ++i) acc += a.X[(size_t)S.ids[i] * d + j];
+      S.mu[j] = acc / (float)m;
+    }
+    __syncthreads();
+  }
+  float my_max_n = 0.f, my_max_c = 0.f;
+  int all_int = 1;
+  for (int i = tid; i < m; i += LEAF_THREADS) {
+    const float* x = a.X + (size_t)S.ids[i] * d;
+    float nacc = 0.f, cacc = 0.f;
+    for (int j = 0; j < d; ++j) {
+      float v = x[j];
+      if (BF16) {
+        float c = v - S.mu[j];
+        float t = bf16_round(c);
+        nacc = __builtin_fmaf(t, t, nacc);
+        cacc = __builtin_fmaf(c, c, cacc);
+      } else {
+        nacc = __builtin_fmaf(v, v, nacc);
+        all_int &= (v == rintf(v));
+      }
+    }
+    if (!BF16) all_int &= (nacc <= 4194304.0f);   // 2^22: every Gram partial sum exact
+    S.nrm[i] = nacc;
+    my_max_n = fmaxf(my_max_n, nacc);
+    my_max_c = fmaxf(my_max_c, cacc);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    my_max_n = fmaxf(my_max_n, __shfl_xor(my_max_n, o));
+    my_max_c = fmaxf(my_max_c, __shfl_xor(my_max_c, o));
+  }
+  if (lane == 0) { S.red[w] = my_max_n; S.red[4 + w] = my_max_c; }
+  if (!all_int) S.flag = 0;
+  __syncthreads();
+  const float max_n = fmaxf(fmaxf(S.red[0], S.red[1]), fmaxf(S.red[2], S.red[3]));
+  const float max_c = sqrtf(fmaxf(fmaxf(S.red[4], S.red[5]), fmaxf(S.red[6], S.red[7])));
+  const bool exact_gram = !BF16 && S.flag;
+  const float eps_c = 2.0f * (float)(d + 4) * 5.9604645e-8f;   // 2 (d+4) 2^-24
+
+  unsigned char* scr = S.scratch[w];
+  float2* myq = reinterpret_cast<float2*>(scr) + lane * QUEUE;
+
+  for (int qb = 0; qb < m; qb += QPB) {
+    const int qbase = qb + w * QPW;
+    if (qbase >= m) continue;                 // whole wave idle in this pass
+    const int qpos = qbase + r32;
+    const bool qok = qpos < m;
+    const float* qrow = a.X + (size_t)S.ids[qok ? qpos : 0] * d;
+    Frag<KC, BF16> qf, cf;
+    const bool one_chunk = d <= KC;
+    if (one_chunk) qf.load(qrow, 0, d, h, S.mu, qok);
+    float lv[KP];
+    int lp[KP];
+#pragma unroll
+    for (int s = 0; s < KP; ++s) { lv[s] = __int_as_float(0x7F800000); lp[s] = -1; }
+    float thr_pair = __int_as_float(0x7F800000);
+    for (int c0 = 0; c0 < m; c0 += TILE) {
+      const int cpos = c0 + r32;
+      const bool cok = cpos < m;
+      const float* crow = a.X + (size_t)S.ids[cok ? cpos : 0] * d;
+      f32x16 acc0 = {0}, acc1 = {0};
+      for (int kc = 0; kc < d; kc += KC) {
+        if (!one_chunk) qf.load(qrow, kc, d, h, S.mu, qok);
+        cf.load(crow, kc, d, h, S.mu, cok);
+        gram_chunk<KC, BF16>(cf, qf, acc0, acc1);
+      }
+      if (lane < TILE) S.tnorm[w][lane] = (c0 + lane < m) ? S.nrm[c0 + lane] : 0.f;
+      wave_sync();
+      // filter this tile into the lane's queue
+      const float thr = fminf(lv[KP - 1], thr_pair);
+      int cnt = 0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        int ci = 8 * (r >> 2) + 4 * h + (r & 3);
+        int cp = c0 + ci;
+        float g = acc0[r] + acc1[r];
+        float sv = S.tnorm[w][ci] - 2.0f * g;
+        bool ok = qok && cp < m && cp != qpos && (sv < lv[KP - 1]) && (sv <= thr);
+        if (ok) myq[cnt] = make_float2(sv, __int_as_float(cp));
+        cnt += ok ? 1 : 0;
+      }
+      for (int q = 0; __any(q < cnt); ++q) {
+        if (q < cnt) {
+          float2 e = myq[q];
+          if (e.x < lv[KP - 1]) list_insert<KP>(lv, lp, e.x, __float_as_int(e.y));
+        }
+      }
+      thr_pair = __shfl_xor(lv[KP - 1], 32);
+      wave_sync();
+    }
+    // ---- merge the two half-lists of each query
+    float2* LA = reinterpret_cast<float2*>(scr);
+    float2* LB = LA + QPW * KP;
+    {
+      float2* mine = h == 0 ? LA : LB;
+#pragma unroll
+      for (int s2 = 0; s2 < KP; ++s2) mine[r32 * KP + s2] = make_float2(lv[s2], __int_as_float(lp[s2]));
+    }
+    wave_sync();
+    float mv[KP];
+    int mp[KP];
+    if (h == 0) {
+      int ia = 0, ib = 0;
+#pragma unroll
+      for (int s2 = 0; s2 < KP; ++s2) {
+        float2 ea = LA[r32 * KP + (ia < KP ? ia : KP - 1)];
+        float2 eb = LB[r32 * KP + (ib < KP ? ib : KP - 1)];
+        float va = ia < KP ? ea.x : __int_as_float(0x7F800000);
+        float vb = ib < KP ? eb.x : __int_as_float(0x7F800000);
+        unsigned pa = ia < KP ? (unsigned)__float_as_int(ea.y) : 0xFFFFFFFFu;
+        unsigned pb2 = ib < KP ? (unsigned)__float_as_int(eb.y) : 0xFFFFFFFFu;
+        bool take_a = (va < vb) || (va == vb && pa <= pb2);
+        mv[s2] = take_a ? va : vb;
+        mp[s2] = (int)(take_a ? pa : pb2);
+        ia += take_a ? 1 : 0;
+        ib += take_a ? 0 : 1;
+      }
+    }
+    wave_sync();
+    int* pb = reinterpret_cast<int*>(scr);            // [QPW][KP] candidate positions
+    float* vbuf = reinterpret_cast<float*>(scr) + QPW * KP;      // [QPW][KP] approximate values
+    float* dex = reinterpret_cast<float*>(scr) + 2 * QPW * KP;   // [QPW][KP] exact distances
+    if (h == 0) {
+#pragma unroll
+      for (int s2 = 0; s2 < KP; ++s2) { pb[r32 * KP + s2] = mp[s2]; vbuf[r32 * KP + s2] = mv[s2]; }
+    }
+    wave_sync();
+    // ---- exact re-rank: 4 (query, candidate) pairs per step, 16 lanes each
+    const int g = lane >> 4, gl = lane & 15;
+    for (int pr = g; pr < QPW * KP; pr += 4) {
+      int qj = pr / KP;
+      int cp = pb[pr];
+      int qp = qbase + qj;
+      bool ok = cp >= 0 && qp < m;
+      const float* xq = a.X + (size_t)S.ids[qp < m ? qp : 0] * d;
+      const float* xc = a.X + (size_t)S.ids[ok ? cp : 0] * d;
+      float dd = dist2_g16(xq, xc, d, gl);
+      if (gl == 0) dex[pr] = ok ? dd : __int_as_float(0x7F800000);
+    }
+    wave_sync();
+    // ---- sort each query's KP (distance, id) keys; blocks of KP over the wave
+    constexpr int R = (QPW * KP) / 64;
+    uint64_t kv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      int e = r * 64 + lane;
+      int cp = pb[e];
+      kv[r] = cp >= 0 ? pack_did(dex[e], S.ids[cp]) : ~0ull;
+    }
+    wave_bitonic<R, KP, uint64_t>(kv, lane);
+    // write rows, check the certificate on slot k-1
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      int e = r * 64 + lane;
+      int qj = e / KP, slot = e % KP;
+      int qp = qbase + qj;
+      if (qp < m && slot < k) {
+        uint32_t qid = S.ids[qp];
+        a.ids[(size_t)qid * k + slot] = key_id(kv[r]);
+        a.dist[(size_t)qid * k + slot] = key_dist(kv[r]);
+        if (slot == k - 1) {
+          // worst rejected candidate: the KP-th approximate value, if the list was full
+          float vlast = vbuf[qj * KP + KP - 1];
+          bool full = pb[qj * KP + KP - 1] >= 0;
+          bool cert = true;
+          if (full && !exact_gram) {
+            float nq = S.nrm[qp];
+            float dt = nq + vlast;                         // approximate distance of the boundary
+            float e32 = eps_c * (nq + max_n);
+            float lb;
+            if (BF16) {
+              float xq = 0.f;
+              const float* xr = a.X + (size_t)qid * d;
+              for (int j = 0; j < d; ++j) { float c = xr[j] - S.mu[j]; xq = __builtin_fmaf(c, c, xq); }
+              float delta = (0.00390625f + 1.2e-7f) * (sqrtf(xq) + max_c) * 1.001f;
+              float rt = sqrtf(fmaxf(dt - e32, 0.f)) - delta;
+              lb = rt > 0.f ? rt * rt * 0.9999f : 0.f;
+            } else {
+              lb = dt - e32;
+            }
+            float dk = key_dist(kv[r]);
+            cert = lb > dk * (1.0f + 2e-6f);
+          }
+          if (!cert) {
+            unsigned long long sl = atomicAdd(&a.diag->fallback_count, 1ull);
+            atomicAdd(&a.diag->leaf_fallback, 1ull);
+            if (sl < (unsigned long long)a.n) {
+              a.fallback[2 * sl] = (uint32_t)L;
+              a.fallback[2 * sl + 1] = (uint32_t)qp;
+            }
+          }
+        }
+      }
+    }
+    wave_sync();
+  }
+}
+
+// Exact row: distances from one member to every other member of its leaf,
+// streamed in chunks of 2048 through an LDS bitonic sort; keeps the first k
+// by (distance, id).
+__global__ __launch_bounds__(256) void k_leaf_exact(LeafArgs a) {
+  __shared__ uint64_t keys[2048 + 64];
+  __shared__ uint64_t best[64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  unsigned long long cnt = a.diag->fallback_count;
+  if (cnt > (unsigned long long)a.n) cnt = (unsigned long long)a.n;
+  for (unsigned long long it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const uint32_t L = a.fallback[2 * it], qp = a.fallback[2 * it + 1];
+    const int64_t off = a.leaf_off[L];
+    const int64_t m = a.leaf_off[L + 1] - off;
+    const uint32_t qid = a.perm[off + qp];
+    const float* xq = a.X + (size_t)qid * a.d;
+    if (tid < 64) best[tid] = ~0ull;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < m; c0 += 2048) {
+      // 16 groups of 16 lanes score candidates c0 + gid, c0 + gid + 16, ...
+      const int gid = tid >> 4, gl = tid & 15;
+      for (int j = gid; j < 2048; j += 16) {
+        int64_t cp = c0 + j;
+        uint64_t key = ~0ull;
+        if (cp < m) {   // uniform across the 16-lane group
+          uint32_t cid = a.perm[off + cp];
+          float dd = dist2_g16(xq, a.X + (size_t)cid * a.d, a.d, gl);
+          if (cp != (int64_t)qp) key = pack_did(dd, cid);
+        }
+        if (gl == 0) keys[j] = key;
+      }
+      if (tid < 64) keys[2048 + tid] = best[tid];
+      __syncthreads();
+      // bitonic sort of 2048 keys (the 64 kept ones ride along below)
+      for (int size = 2; size <= 2048; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+          for (int e = tid; e < 2048; e += 256) {
+            int p = e ^ stride;
+            if (p > e) {
+              bool asc = (e & size) == 0;
+              uint64_t x = keys[e], y = keys[p];
+              if (asc ? (x > y) : (x < y)) { keys[e] = y; keys[p] = x; }
+            }
+          }
+          __syncthreads();
+        }
+      }
+      // merge the sorted chunk's first k with the kept list (wave 0)
+      if (wv == 0) {
+        uint64_t x = lane < a.k ? keys[lane] : ~0ull;
+        uint64_t y = lane < a.k ? keys[2048 + lane] : ~0ull;
+        // 128-element sort of the two lists in registers, keep first k
+        uint64_t v[2] = {x, y};
+        wave_bitonic<2, 128, uint64_t>(v, lane);
+        if (lane < 64) best[lane] = lane < a.k ? v[0] : ~0ull;
+      }
+      __syncthreads();
+    }
+    if (tid < a.k) {
+      a.ids[(size_t)qid * a.k + tid] = key_id(best[tid]);
+      a.dist[(size_t)qid * a.k + tid] = key_dist(best[tid]);
+    }
+    __syncthreads();
+  }
+}
+
+template <int KC, int KP, bool BF16>
+hipError_t launch_leaf_t(const LeafArgs& a, hipStream_t s) {
+  size_t shm = sizeof(LeafShared<KP, BF16>);
+  auto kern = k_leaf<KC, KP, BF16>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)a.n_leaves), dim3(LEAF_THREADS), shm, s, a);
+  return hipGetLastError();
+}
+
+template <int KC, bool BF16>
+hipError_t launch_leaf_kp(const LeafArgs& a, hipStream_t s) {
+  if (a.kp <= 16) return launch_leaf_t<KC, 16, BF16>(a, s);
+  if (a.kp <= 32) return launch_leaf_t<KC, 32, BF16>(a, s);
+  return launch_leaf_t<KC, 64, BF16>(a, s);
+}
+
+}  // namespace
+
+hipError_t launch_leaf(const LeafArgs& a, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_fill_u32((uint32_t*)&a.diag->fallback_count, 0u, 2, s)) != hipSuccess) return e;
+  if (a.precision == KNNG_BF16) {
+    if (a.d <= 32) e = launch_leaf_kp<32, true>(a, s);
+    else if (a.d <= 64) e = launch_leaf_kp<64, true>(a, s);
+    else e = launch_leaf_kp<128, true>(a, s);
+  } else {
+    if (a.d <= 32) e = launch_leaf_kp<32, false>(a, s);
+    else if (a.d <= 64) e = launch_leaf_kp<64, false>(a, s);
+    else e = launch_leaf_kp<128, false>(a, s);
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_leaf_exact, dim3(1024), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace knng
