@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Throughput of the full k-NN graph build on one MI355X.
+
+A step is one call of the whole method (T random divisions, leaf k-NN per
+division, merge, propagation rounds) over the resident synthetic point set.
+Prints one JSON line: points/s, recall@10 against exact k-NN on sampled
+queries, the roofline position of the dominant kernel (measured live with HIP
+events at every stage boundary) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import datagen  # noqa: E402
+
+PEAK_FP32_MFMA = 157.3     # TFLOP/s, MI355X dense FP32 matrix
+PEAK_BF16_MFMA = 2500.0    # TFLOP/s, MI355X dense BF16 matrix
+PEAK_HBM = 8000.0          # GB/s
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def exact_kth(X, queries, k, block=131072):
+    """Exact k-th neighbour distance (float64, self excluded) of each query by
+    blocked brute force over all points: the recall reference."""
+    Q = X[queries].astype(np.float64)
+    nq = (Q * Q).sum(1)
+    best = np.full((len(queries), k + 1), np.inf)
+    for s in range(0, X.shape[0], block):
+        B = X[s:s + block].astype(np.float64)
+        D = nq[:, None] + (B * B).sum(1)[None, :] - 2.0 * (Q @ B.T)
+        own = (queries >= s) & (queries < s + len(B))
+        D[np.nonzero(own)[0], queries[own] - s] = np.inf
+        best = np.sort(np.concatenate([best, np.partition(D, k, axis=1)[:, :k + 1]], axis=1), axis=1)[:, :k + 1]
+    return np.maximum(best[:, k - 1], 0.0)
+
+
+def recall_at(X, ids, queries, kth, k):
+    """Tie-aware recall@k: a returned neighbour counts when its distance is
+    within the exact k-th distance (plus float64 rounding of the expanded form)."""
+    hits = 0
+    for r, i in enumerate(queries):
+        row = ids[i, :k].astype(np.int64)
+        row = row[(row >= 0) & (row != i)]
+        if len(row) == 0:
+            continue
+        dd = ((X[row].astype(np.float64) - X[i].astype(np.float64)) ** 2).sum(1)
+        hits += int((dd <= kth[r] * (1 + 1e-9) + 1e-9).sum())
+    return hits / (len(queries) * k)
+
+
+def leaf_flops(K, kp):
+    """Algorithmic FLOP of one leaf launch per division: 2 d sum(m^2) (full Gram)."""
+    out = []
+    for t in range(kp.T):
+        off, _, _ = K.tree_shape(kp, t)
+        m = np.diff(np.asarray(off, dtype=np.int64))
+        out.append(2.0 * kp.d * float((m.astype(np.float64) ** 2).sum()))
+    return out
+
+
+def read_traffic(kernel_src, name):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line:
+            a, b = line.split(":", 1)
+            kv[a.strip()] = b.strip()
+    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    if kv.get("source_sha") != sha:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, n_sample):
+    """The CPU oracle (float64, single-threaded NumPy) on a bounded sample of
+    the same workload: n_sample points drawn from the same generator."""
+    from oracle import knng_oracle as O
+    Xs = datagen.make(w, n=n_sample)
+    op = O.Params(n=n_sample, d=w.d, k=w.k, T=w.T, leaf_max=w.leaf_max, leaf_cap_cycle=w.leaf_cap_cycle,
+                  q_lo_pm=w.q_lo_pm, q_hi_pm=w.q_hi_pm, rounds=w.rounds, pairwise=True, seed=w.seed + 1)
+    t0 = time.perf_counter()
+    O.build(Xs, op)
+    dt = time.perf_counter() - t0
+    return {"value": round(n_sample / dt, 2), "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"whole method on {n_sample} points of the same generator ({dt:.1f} s); "
+                      f"host has {os.cpu_count()} logical cores, the oracle runs on one"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sift1m", choices=sorted(datagen.WORKLOADS))
+    ap.add_argument("--T", type=int, default=None, help="override the number of divisions")
+    ap.add_argument("--rounds", type=int, default=None, help="override the propagation rounds")
+    ap.add_argument("--queries", type=int, default=1000, help="recall sample size")
+    ap.add_argument("--cpu-sample", type=int, default=6000, help="points for the CPU oracle leg (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
+              f"(the multi-GPU sharding is a design in DESIGN.md, not code).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1307_7852_amd as K
+
+    w = datagen.WORKLOADS[args.workload]
+    T = args.T if args.T is not None else w.T
+    rounds = args.rounds if args.rounds is not None else w.rounds
+    dev = torch.device("cuda:0")
+    log(f"generating {w.name}: n={w.n} d={w.d}")
+    t0 = time.time()
+    X = datagen.make(w)
+    log(f"  {time.time() - t0:.1f}s")
+    kp = K.Params(n=w.n, d=w.d, k=w.k, T=T, leaf_max=w.leaf_max, leaf_cap_cycle=w.leaf_cap_cycle,
+                  q_lo_pm=w.q_lo_pm, q_hi_pm=w.q_hi_pm, rounds=rounds, pairwise=1,
+                  precision=K.BF16 if w.precision == "bf16" else K.FP32, rerank_m=w.rerank_m, seed=w.seed + 1)
+    X_t = torch.from_numpy(X).to(dev)
+    ws = K.alloc_workspace(kp, K.OP_BUILD, dev)
+    ids = torch.empty((w.n, w.k), dtype=torch.int32, device=dev)
+    dist = torch.empty((w.n, w.k), dtype=torch.float32, device=dev)
+    log(f"workspace {ws.numel() / 2**30:.2f} GiB")
+    for i in range(args.warmup):
+        K.build(kp, X_t, ids, dist, ws)
+        torch.cuda.synchronize()
+        log(f"warmup {i} done")
+
+    stages = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        stages.append(K.build_timed(kp, X_t, ids, dist, ws))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1000.0 * wall / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step")
+    diag = K.read_diag(kp, ws, K.OP_BUILD)
+
+    # stage totals (ms per step, averaged)
+    div_ms = float(np.mean([sum(s["divide"]) for s in stages]))
+    leaf_ms = float(np.mean([sum(s["leaf"]) for s in stages]))
+    merge_ms = float(np.mean([s["merge"] for s in stages]))
+    prop_ms = float(np.mean([sum(s["rounds"]) for s in stages]))
+    leaf_launch_ms = float(np.mean([np.mean(s["leaf"]) for s in stages]))
+    flops = leaf_flops(K, kp)
+    leaf_tflops = (float(np.mean(flops)) / (leaf_launch_ms * 1e-3)) / 1e12
+    peak = PEAK_BF16_MFMA if kp.precision == K.BF16 else PEAK_FP32_MFMA
+    src = os.path.join(ROOT, "paper_1307_7852_amd", "csrc", "leaf.hip")
+    traffic = read_traffic(src, "leaf_knn_sift1m" if args.workload == "sift1m" else f"leaf_knn_{args.workload}")
+    # propagation: algorithmic bytes of the last round from its candidate count
+    U = diag["prop_candidates"]
+    nk = w.n * w.k
+    prop_bytes = (4.0 * w.k * w.k * w.n + 4.0 * w.d * (U + w.n) + 24.0 * nk + 16.0 * U)
+    prop_round_ms = prop_ms / max(1, rounds)
+    prop_gbs = prop_bytes / (prop_round_ms * 1e-3) / 1e9 if rounds else 0.0
+
+    ids_h = ids.cpu().numpy()
+    queries = datagen.query_sample(w.n, args.queries, w.seed)
+    log("exact reference for recall")
+    t0 = time.time()
+    kth = exact_kth(X, queries, min(10, w.k))
+    rec10 = recall_at(X, ids_h, queries, kth, min(10, w.k))
+    log(f"  recall@10={rec10:.4f} ({time.time() - t0:.1f}s)")
+
+    out = {
+        "metric": "points/sec for full k-NN graph at recall@10>=0.95; leaf MFMA util; propagate HBM GB/s",
+        "value": round(w.n / (ms_per_step * 1e-3), 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if kp.precision == K.BF16 else "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "d": w.d, "k": w.k, "T": T, "leaf_max": w.leaf_max,
+                   "rounds": rounds, "pairwise": True, "leaf_gram": "bf16" if kp.precision == K.BF16 else "fp32",
+                   "leaf_cap_cycle": w.leaf_cap_cycle, "split_permille": [w.q_lo_pm, w.q_hi_pm]},
+        "recall@10": round(rec10, 5),
+        "recall_queries": int(len(queries)),
+        "roofline": {"kernel": "k_leaf (leaf k-NN, one launch per division)", "bound": "mfma",
+                     "achieved": round(leaf_tflops, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(leaf_tflops / peak, 4), "traffic": traffic,
+                     "flop_per_launch": float(np.mean(flops)), "launch_ms": round(leaf_launch_ms, 4)},
+        "stages_ms_per_step": {"divide": round(div_ms, 3), "leaf": round(leaf_ms, 3), "merge": round(merge_ms, 3),
+                               "propagate": round(prop_ms, 3)},
+        "propagate": {"achieved_GBps": round(prop_gbs, 1), "peak_GBps": PEAK_HBM,
+                      "frac": round(prop_gbs / PEAK_HBM, 4), "candidates_per_point": round(U / w.n, 2),
+                      "algorithmic_bytes_per_round": prop_bytes},
+        "leaf_rows_fallback_per_step": diag["leaf_rows_fallback"] / max(1, args.warmup + args.steps),
+        "paper_context": "single-thread 2.66 GHz CPU, 1M SIFT: ~810-820 points/s at 95% accuracy (derived from "
+                         "'about 1% of the brute-force time', Section 4); different data and hardware",
+    }
+    if args.cpu_sample > 0:
+        log(f"cpu baseline on {args.cpu_sample} points")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

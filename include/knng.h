@@ -177,6 +177,13 @@ int knng_propagate(const knng_params* p, const float* X, uint32_t* ids, float* d
 int knng_build(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
                void* stream);
 
+/* knng_build with a HIP event at every stage boundary; waits for the stream
+ * at the end.  ms_out (host, at least 2T + 1 + rounds entries) receives the
+ * GPU time of: divide t (entries 2t), leaf k-NN t (2t + 1) for t < T, the
+ * merge (2T), then each propagation round (2T + 1 + r).                    */
+int knng_build_timed(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
+                     void* stream, float* ms_out, int ms_cap);
+
 /* Copies the diagnostics of the last call that used workspace `ws` to the
  * host; waits for `stream`.                                                */
 int knng_read_diag(const knng_params* p, const void* ws, int op, knng_diag* out, void* stream);

@@ -4,10 +4,10 @@ ABI of include/knng.h.  This package is the thin Python side: the ctypes
 binding plus torch helpers for device buffers."""
 from . import _lib
 from ._lib import (BF16, FP32, NONE, OP_BUILD, OP_DIVIDE, OP_LEAF, OP_MERGE, OP_PROPAGATE, SPLIT_PCA, SPLIT_RP,
-                   KnngError, Params, build, divide, leaf_knn, merge, propagate, read_diag, tree_shape,
+                   KnngError, Params, build, build_timed, divide, leaf_knn, merge, propagate, read_diag, tree_shape,
                    workspace_bytes)
 
-__all__ = ["Params", "KnngError", "build", "divide", "leaf_knn", "merge", "propagate", "read_diag", "tree_shape",
+__all__ = ["Params", "KnngError", "build", "build_timed", "divide", "leaf_knn", "merge", "propagate", "read_diag", "tree_shape",
            "workspace_bytes", "alloc_workspace", "knn_graph", "NONE", "FP32", "BF16", "SPLIT_RP", "SPLIT_PCA",
            "OP_DIVIDE", "OP_LEAF", "OP_MERGE", "OP_PROPAGATE", "OP_BUILD"]
 

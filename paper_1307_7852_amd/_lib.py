@@ -91,6 +91,7 @@ def _load():
         "knng_propagate": (i32, [P, vp, vp, vp, i32, vp, sz, vp]),
         "knng_build": (i32, [P, vp, vp, vp, vp, sz, vp]),
         "knng_read_diag": (i32, [P, vp, i32, ctypes.POINTER(_CDiag), vp]),
+        "knng_build_timed": (i32, [P, vp, vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_float), i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -101,7 +102,7 @@ def _load():
 
 _lib = _load()
 EXPORTS = ["knng_status_str", "knng_last_error", "knng_workspace_bytes", "knng_tree_shape", "knng_divide",
-           "knng_leaf_knn", "knng_merge", "knng_propagate", "knng_build", "knng_read_diag"]
+           "knng_leaf_knn", "knng_merge", "knng_propagate", "knng_build", "knng_read_diag", "knng_build_timed"]
 
 
 def _status_name(s: int) -> str:
@@ -173,6 +174,17 @@ def build(p: Params, X, ids, dist, ws, stream=None):
     cp = p.c()
     _check(_lib.knng_build(ctypes.byref(cp), _ptr(X), _ptr(ids), _ptr(dist), _ptr(ws), ws.numel() * ws.element_size(),
                            _stream(stream)))
+
+
+def build_timed(p: Params, X, ids, dist, ws, stream=None) -> dict:
+    """knng_build with per-stage GPU times (ms); waits for the stream."""
+    cp = p.c()
+    nst = 2 * p.T + 1 + p.rounds
+    buf = (ctypes.c_float * nst)()
+    _check(_lib.knng_build_timed(ctypes.byref(cp), _ptr(X), _ptr(ids), _ptr(dist), _ptr(ws),
+                                 ws.numel() * ws.element_size(), _stream(stream), buf, nst))
+    v = list(buf)
+    return {"divide": v[0:2 * p.T:2], "leaf": v[1:2 * p.T:2], "merge": v[2 * p.T], "rounds": v[2 * p.T + 1:]}
 
 
 def read_diag(p: Params, ws, op: int, stream=None) -> dict:

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -252,7 +253,8 @@ int leaf_core(const knng_params& p, const float* X, const uint32_t* perm, const 
   return KNNG_OK;
 }
 
-int prop_core(const knng_params& p, const float* X, uint32_t* ids, float* dist, int rounds, char* ws, hipStream_t s) {
+int prop_core(const knng_params& p, const float* X, uint32_t* ids, float* dist, int rounds, char* ws, hipStream_t s,
+              const std::function<hipError_t(int)>& after_round = nullptr) {
   PropLayout L = prop_layout(p);
   size_t nk = (size_t)p.n * p.k;
   uint32_t* tids = (uint32_t*)(ws + L.tmp_ids);
@@ -275,10 +277,12 @@ int prop_core(const knng_params& p, const float* X, uint32_t* ids, float* dist, 
     a.bucket = (uint32_t*)(ws + L.bucket);
     a.diag = (DiagDev*)(ws + L.diag);
     HIP_TRY(launch_propagate_round(a, s));
+    if (after_round && !(r == rounds - 1 && rounds % 2 == 1)) HIP_TRY(after_round(r));
   }
   if (rounds % 2 == 1) {
     HIP_TRY(hipMemcpyAsync(ids, tids, nk * 4, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(dist, tdist, nk * 4, hipMemcpyDeviceToDevice, s));
+    if (after_round) HIP_TRY(after_round(rounds - 1));   // the last round includes its copy back
   }
   return KNNG_OK;
 }
@@ -500,8 +504,8 @@ int knng_propagate(const knng_params* p, const float* X, uint32_t* ids, float* d
   return prop_core(*p, X, ids, dist, rounds, (char*)ws, s);
 }
 
-int knng_build(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
-               void* stream) {
+static int build_impl(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
+                      void* stream, std::vector<hipEvent_t>* ev) {
   int st = validate(p);
   if (st) return st;
   if (!X || !ids || !dist || !ws) return fail(KNNG_EINVAL, "null array argument");
@@ -538,18 +542,50 @@ int knng_build(const knng_params* p, const float* X, uint32_t* ids, float* dist,
   int64_t* leaf_off = (int64_t*)(w + B.leaf_off);
   // every sub-stage keeps its diagnostics at the start of the shared region
   HIP_TRY(zero_diag(sub, s));
+  auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord((*ev)[i], s) : hipSuccess; };
+  HIP_TRY(mark(0));
   for (int t = 0; t < p->T; ++t) {
     st = divide_core(*p, t, *plans[t], w + B.plans + plan_off[t], X, nullptr, nullptr, perm, leaf_off, sub, D, s);
     if (st) return st;
+    HIP_TRY(mark(1 + 2 * t));
     st = leaf_core(*p, X, perm, leaf_off, plans[t]->n_leaves(), lists_ids + t * nk, lists_dist + t * nk, sub, s);
     if (st) return st;
+    HIP_TRY(mark(2 + 2 * t));
   }
   HIP_TRY(launch_merge(p->n, p->k, p->T, lists_ids, lists_dist, ids, dist, s));
+  HIP_TRY(mark(1 + 2 * p->T));
   if (p->rounds > 0) {
-    st = prop_core(*p, X, ids, dist, p->rounds, sub, s);
+    st = prop_core(*p, X, ids, dist, p->rounds, sub, s, [&](int r) { return mark(2 + 2 * p->T + r); });
     if (st) return st;
   }
   return KNNG_OK;
+}
+
+int knng_build(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
+               void* stream) {
+  return build_impl(p, X, ids, dist, ws, ws_bytes, stream, nullptr);
+}
+
+int knng_build_timed(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
+                     void* stream, float* ms_out, int ms_cap) {
+  int st = validate(p);
+  if (st) return st;
+  int nst = 2 * p->T + 1 + p->rounds;
+  if (!ms_out || ms_cap < nst) return fail(KNNG_EINVAL, "ms_out needs %d entries (got %d)", nst, ms_cap);
+  std::vector<hipEvent_t> ev(nst + 1, nullptr);
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& f : ev) if (f) (void)hipEventDestroy(f);
+      return fail(KNNG_EHIP, "hipEventCreate failed");
+    }
+  st = build_impl(p, X, ids, dist, ws, ws_bytes, stream, &ev);
+  if (st == KNNG_OK) {
+    hipError_t e = hipEventSynchronize(ev[nst]);
+    for (int i = 0; i < nst && e == hipSuccess; ++i) e = hipEventElapsedTime(&ms_out[i], ev[i], ev[i + 1]);
+    if (e != hipSuccess) st = fail(KNNG_EHIP, "event timing failed: %s", hipGetErrorString(e));
+  }
+  for (auto& f : ev) (void)hipEventDestroy(f);
+  return st;
 }
 
 int knng_read_diag(const knng_params* p, const void* ws, int op, knng_diag* out, void* stream) {
