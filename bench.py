@@ -97,7 +97,7 @@ def cpu_baseline(w, n_sample):
     op = O.Params(n=n_sample, d=w.d, k=w.k, T=w.T, leaf_max=w.leaf_max, leaf_cap_cycle=w.leaf_cap_cycle,
                   q_lo_pm=w.q_lo_pm, q_hi_pm=w.q_hi_pm, rounds=w.rounds, pairwise=True, seed=w.seed + 1)
     t0 = time.perf_counter()
-    O.build(Xs, op)
+    O.build(Xs, op, split=w.split)
     dt = time.perf_counter() - t0
     return {"value": round(n_sample / dt, 2), "unit": "points/s", "cores": 1, "kind": "oracle",
             "sample": f"whole method on {n_sample} points of the same generator ({dt:.1f} s); "
@@ -113,7 +113,7 @@ def main():
     ap.add_argument("--T", type=int, default=None, help="override the number of divisions")
     ap.add_argument("--rounds", type=int, default=None, help="override the propagation rounds")
     ap.add_argument("--queries", type=int, default=1000, help="recall sample size")
-    ap.add_argument("--cpu-sample", type=int, default=6000, help="points for the CPU oracle leg (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=20000, help="points for the CPU oracle leg (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
@@ -133,7 +133,8 @@ def main():
     log(f"  {time.time() - t0:.1f}s")
     kp = K.Params(n=w.n, d=w.d, k=w.k, T=T, leaf_max=w.leaf_max, leaf_cap_cycle=w.leaf_cap_cycle,
                   q_lo_pm=w.q_lo_pm, q_hi_pm=w.q_hi_pm, rounds=rounds, pairwise=1,
-                  precision=K.BF16 if w.precision == "bf16" else K.FP32, rerank_m=w.rerank_m, seed=w.seed + 1)
+                  precision=K.BF16 if w.precision == "bf16" else K.FP32, rerank_m=w.rerank_m, seed=w.seed + 1,
+                  split=K.SPLIT_PCA if w.split == "pca" else K.SPLIT_RP, pca_iters=16)
     X_t = torch.from_numpy(X).to(dev)
     ws = K.alloc_workspace(kp, K.OP_BUILD, dev)
     ids = torch.empty((w.n, w.k), dtype=torch.int32, device=dev)
@@ -196,7 +197,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "k": w.k, "T": T, "leaf_max": w.leaf_max,
                    "rounds": rounds, "pairwise": True, "leaf_gram": "bf16" if kp.precision == K.BF16 else "fp32",
-                   "leaf_cap_cycle": w.leaf_cap_cycle, "split_permille": [w.q_lo_pm, w.q_hi_pm]},
+                   "leaf_cap_cycle": w.leaf_cap_cycle, "split_permille": [w.q_lo_pm, w.q_hi_pm],
+                   "split": "principal direction (16 FP32 power iterations on 256 samples)" if w.split == "pca"
+                   else "random projection"},
         "recall@10": round(rec10, 5),
         "recall_queries": int(len(queries)),
         "roofline": {"kernel": "k_leaf (leaf k-NN, one launch per division)", "bound": "mfma",

@@ -43,19 +43,23 @@ class Workload:
     q_hi_pm: int = 500
     precision: str = "fp32"      # leaf Gram precision
     rerank_m: int = 6
+    split: str = "rp"            # "rp": random projection; "pca": random principal direction
 
 
 WORKLOADS = {
     # 16 isotropic Gaussians, means U[-10,10]^32, sigma 1.
     "gauss10k": Workload("gauss10k", 10_000, 32, 10, 4, 256, 2, "gauss", 16, SEED_BASE + 1),
-    # SIFT-like: 1000 clusters, integer features in [0,255] stored as fp32.
-    "sift1m": Workload("sift1m", 1_000_000, 128, 10, 8, 512, 3, "sift", 1000, SEED_BASE + 2),
+    # SIFT-like: 1000 clusters, integer features in [0,255] stored as fp32;
+    # split by random principal directions, the paper's own choice.
+    "sift1m": Workload("sift1m", 1_000_000, 128, 10, 8, 512, 3, "sift", 1000, SEED_BASE + 2, split="pca"),
+    # The same with random-projection splits.
+    "sift1m_rp": Workload("sift1m_rp", 1_000_000, 128, 10, 8, 512, 3, "sift", 1000, SEED_BASE + 2),
     # Same data; BF16 Gram with FP32 re-rank, uneven leaves 64..1024.
     "sift1m_bf16_uneven": Workload("sift1m_bf16_uneven", 1_000_000, 128, 10, 8, 512, 3, "sift", 1000,
                                    SEED_BASE + 2, leaf_cap_cycle=3, q_lo_pm=300, q_hi_pm=700,
-                                   precision="bf16", rerank_m=16),
+                                   precision="bf16", rerank_m=16, split="pca"),
     # GIST-like: 960-d, intrinsic dimension 32, nonnegative, unit norm.
-    "gist1m": Workload("gist1m", 1_000_000, 960, 20, 8, 512, 3, "gist", 500, SEED_BASE + 4),
+    "gist1m": Workload("gist1m", 1_000_000, 960, 20, 8, 512, 3, "gist", 500, SEED_BASE + 4, split="pca"),
     # SIFT-like at 4M points, fresh clusters.
     "sift4m": Workload("sift4m", 4_000_000, 128, 10, 6, 512, 2, "sift", 4000, SEED_BASE + 5),
 }

@@ -224,18 +224,27 @@ __global__ __launch_bounds__(DIV_THREADS) void k_part_scatter(DivideLevelArgs a)
   }
 }
 
-// Principal direction of a node sample by FP32 power iteration.
+// Principal direction of a node sample by FP32 power iteration (Section 3.4
+// takes the principal direction of points sampled from the subset).  When the
+// sample fits (SAMPLE_LDS) it is copied to LDS once, with every load in
+// flight together, centred there, and each iteration reads it twice:
+// t = Y v (a thread per sample row; rows padded by one float so the threads'
+// column reads fall in distinct banks) and w = Y^T t (a thread per feature).
+// Otherwise the same two passes read the rows from global memory.
+template <bool SAMPLE_LDS>
 __global__ __launch_bounds__(DIV_THREADS) void k_pca_dirs(DivideLevelArgs a) {
   extern __shared__ float smem[];
+  const int d = a.d;
+  const int ld = d + 1;           // padded row stride in LDS
   float* mu = smem;               // d
-  float* v = mu + a.d;            // d
-  float* w = v + a.d;             // d
-  float* tt = w + a.d;            // 256
+  float* v = mu + d;              // d
+  float* tt = v + d;              // 256
+  float* Y = tt + 256;            // 256 x (d + 1) when SAMPLE_LDS
   __shared__ uint32_t rows[256];
   __shared__ float red[DIV_THREADS / 64];
   __shared__ int redi[DIV_THREADS / 64];
   const SegDesc sd = a.segs[blockIdx.x];
-  const int d = a.d;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint32_t m = sd.m;
   uint32_t s = m < 256 ? m : 256;
   uint32_t wd = m / s;
@@ -245,17 +254,51 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_dirs(DivideLevelArgs a) {
                    (uint32_t)(rand64(a.seed, TAG_SAMPLE, (uint32_t)a.t, sd.v, threadIdx.x) % wd);
     rows[threadIdx.x] = a.perm_in[sd.off + pos];
   }
+  for (int j = threadIdx.x; j < d; j += DIV_THREADS) v[j] = rp_entry(a.seed, (uint32_t)a.t, sd.v, (uint32_t)j);
   __syncthreads();
-  for (int j = threadIdx.x; j < d; j += DIV_THREADS) {
-    float acc = 0.f;
-    for (uint32_t i = 0; i < s; ++i) acc += a.X[(size_t)rows[i] * d + j];
-    mu[j] = acc / (float)s;
-    v[j] = rp_entry(a.seed, (uint32_t)a.t, sd.v, (uint32_t)j);
+  if constexpr (SAMPLE_LDS) {
+    // raw sample -> LDS: element e = (row, float4 column), 8 loads in flight per thread
+    const int c4 = d >> 2, tot = (int)s * c4;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += DIV_THREADS * 8) {
+      float4 buf[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int e = e0 + u * DIV_THREADS;
+        buf[u] = e < tot ? ((const float4*)(a.X + (size_t)rows[e / c4] * d))[e % c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int e = e0 + u * DIV_THREADS;
+        if (e < tot) {
+          float* yr = Y + (e / c4) * ld + 4 * (e % c4);
+          yr[0] = buf[u].x; yr[1] = buf[u].y; yr[2] = buf[u].z; yr[3] = buf[u].w;
+        }
+      }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < d; j += DIV_THREADS) {
+      float acc = 0.f;
+      for (uint32_t i = 0; i < s; ++i) acc += Y[i * ld + j];
+      mu[j] = acc / (float)s;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < d; j += DIV_THREADS)
+      for (uint32_t i = 0; i < s; ++i) Y[i * ld + j] -= mu[j];
+  } else {
+    for (int j = threadIdx.x; j < d; j += DIV_THREADS) {
+      float acc = 0.f;
+      for (uint32_t i = 0; i < s; ++i) acc += a.X[(size_t)rows[i] * d + j];
+      mu[j] = acc / (float)s;
+    }
   }
   __syncthreads();
+  auto yval = [&](uint32_t i, int j) -> float {
+    if constexpr (SAMPLE_LDS) return Y[i * ld + j];
+    else return a.X[(size_t)rows[i] * d + j] - mu[j];
+  };
   auto block_sum = [&](float x) -> float {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    if (lane == 0) red[wv] = x;
     __syncthreads();
     float r = 0.f;
     for (int i = 0; i < DIV_THREADS / 64; ++i) r += red[i];
@@ -271,23 +314,35 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_dirs(DivideLevelArgs a) {
   __syncthreads();
   for (int itr = 0; itr < a.pca_iters; ++itr) {
     if (threadIdx.x < s) {
-      const float* x = a.X + (size_t)rows[threadIdx.x] * d;
-      float acc = 0.f;
-      for (int j = 0; j < d; ++j) acc += (x[j] - mu[j]) * v[j];
-      tt[threadIdx.x] = acc;
+      float acc0 = 0.f, acc1 = 0.f;
+      int j = 0;
+      for (; j + 1 < d; j += 2) {
+        acc0 = __builtin_fmaf(yval(threadIdx.x, j), v[j], acc0);
+        acc1 = __builtin_fmaf(yval(threadIdx.x, j + 1), v[j + 1], acc1);
+      }
+      for (; j < d; ++j) acc0 = __builtin_fmaf(yval(threadIdx.x, j), v[j], acc0);
+      tt[threadIdx.x] = acc0 + acc1;
     }
     __syncthreads();
     float sq = 0.f;
-    for (int j = threadIdx.x; j < d; j += DIV_THREADS) {
-      float acc = 0.f;
-      for (uint32_t i = 0; i < s; ++i) acc += (a.X[(size_t)rows[i] * d + j] - mu[j]) * tt[i];
-      w[j] = acc;
-      sq += acc * acc;
+    float wj[(4096 + DIV_THREADS - 1) / DIV_THREADS];
+    int nj = 0;
+    for (int j = threadIdx.x; j < d; j += DIV_THREADS, ++nj) {
+      float acc0 = 0.f, acc1 = 0.f;
+      uint32_t i = 0;
+      for (; i + 1 < s; i += 2) {
+        acc0 = __builtin_fmaf(yval(i, j), tt[i], acc0);
+        acc1 = __builtin_fmaf(yval(i + 1, j), tt[i + 1], acc1);
+      }
+      for (; i < s; ++i) acc0 = __builtin_fmaf(yval(i, j), tt[i], acc0);
+      wj[nj] = acc0 + acc1;
+      sq += wj[nj] * wj[nj];
     }
     sq = block_sum(sq);
     if (sq > 0.f) {
       float iv = 1.0f / sqrtf(sq);
-      for (int j = threadIdx.x; j < d; j += DIV_THREADS) v[j] = w[j] * iv;
+      nj = 0;
+      for (int j = threadIdx.x; j < d; j += DIV_THREADS, ++nj) v[j] = wj[nj] * iv;
     }
     __syncthreads();
   }
@@ -303,7 +358,7 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_dirs(DivideLevelArgs a) {
     int oj = __shfl_xor(bj, o);
     if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
   }
-  if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6] = best; redi[threadIdx.x >> 6] = bj; }
+  if (lane == 0) { red[wv] = best; redi[wv] = bj; }
   __syncthreads();
   best = red[0]; bj = redi[0];
   for (int i = 1; i < DIV_THREADS / 64; ++i)
@@ -345,8 +400,19 @@ hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s) {
   hipError_t e;
   if ((e = launch_fill_u32(a.hist, 0u, (size_t)a.n_segs * HIST_TOTAL, s)) != hipSuccess) return e;
   if (a.pca_iters > 0 && !a.dirs) {
-    size_t shm = (size_t)(3 * a.d + 256) * sizeof(float);
-    hipLaunchKernelGGL(k_pca_dirs, dim3(a.n_segs), dim3(DIV_THREADS), shm, s, a);
+    size_t base = (size_t)(2 * a.d + 256) * sizeof(float);
+    size_t big = base + (size_t)256 * (a.d + 1) * sizeof(float);
+    if (big <= 150 * 1024) {
+      static bool attr = false;
+      if (!attr) {
+        e = hipFuncSetAttribute((const void*)k_pca_dirs<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+      }
+      hipLaunchKernelGGL(k_pca_dirs<true>, dim3(a.n_segs), dim3(DIV_THREADS), big, s, a);
+    } else {
+      hipLaunchKernelGGL(k_pca_dirs<false>, dim3(a.n_segs), dim3(DIV_THREADS), base, s, a);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_proj_hist0, dim3(a.n_split), dim3(DIV_THREADS), (size_t)a.d * sizeof(float), s, a);

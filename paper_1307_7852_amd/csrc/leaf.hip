@@ -1,7 +1,9 @@
 // Exact k-NN inside every leaf subset (Section 3.1's brute-force subgraph).
 //
-// One workgroup (4 waves) per leaf.  Each wave owns 32 queries at a time and
-// streams the leaf's members through MFMA in tiles of 32 candidates:
+// One workgroup (4 waves) per leaf.  The leaf's members stream through LDS in
+// tiles of 32 candidates x KC features (double-buffered, staged once for all
+// four waves, rows padded so the MFMA operand reads are bank-conflict free).
+// Each wave owns 32 queries (fragments in registers) and computes
 //   G[c][q] = x_c . x_q         (v_mfma_f32_32x32x2_f32, or the BF16 form
 //                                v_mfma_f32_32x32x16_bf16 on leaf-centred data)
 //   s[c][q] = |x_c|^2 - 2 G     (the query's own norm is constant per row)
@@ -9,11 +11,14 @@
 // best KP candidates in a sorted register list fed through a small LDS
 // queue, so lanes with nothing to insert do not stall the others.  The two
 // lanes sharing a query exchange thresholds after every tile and merge their
-// lists at the end.  The KP survivors are re-scored with the canonical FP32
-// distance, sorted by (distance, id), and the first k written.  A row whose
-// k-th exact distance is not safely below every rejected candidate's lower
-// bound (from the Gram's error bound) is redone exactly by k_leaf_exact.
+// lists in registers at the end.  The KP survivors are re-scored with the
+// canonical FP32 distance, sorted by (distance, id), and the first k written.
+// A row whose k-th exact distance is not safely below every rejected
+// candidate's lower bound (from the Gram's error bound) is redone exactly by
+// k_leaf_exact.
 #include "knng_dev.h"
+
+#include <type_traits>
 
 namespace knng {
 
@@ -26,7 +31,8 @@ constexpr int LEAF_THREADS = 256;
 constexpr int QPW = 32;            // queries per wave
 constexpr int QPB = 128;           // queries per block pass
 constexpr int TILE = 32;           // candidates per tile
-constexpr int QUEUE = 16;          // per-lane queue slots (one tile's share)
+constexpr int QUEUE = 8;           // per-lane queue slots (half a tile's share)
+constexpr int MU_MAX = 2048;       // BF16 path: d <= 2048
 
 template <int KP>
 __device__ __forceinline__ void list_insert(float (&v)[KP], int (&p)[KP], float x, int px) {
@@ -44,83 +50,140 @@ __device__ __forceinline__ void list_insert(float (&v)[KP], int (&p)[KP], float 
   p[0] = t0 ? px : p[0];
 }
 
-__device__ __forceinline__ float4 ld4(const float* p) { return *(const float4*)p; }
+// (value, position) order with the empty entry (-1 as unsigned) last.
+__device__ __forceinline__ bool vp_less(float va, int pa, float vb, int pb) {
+  return va < vb || (va == vb && (unsigned)pa < (unsigned)pb);
+}
 
-constexpr int MU_MAX = 2048;        // BF16 path: d <= 2048
-
-// Per-wave scratch, reused by phase: the tile loop's queues (64 lanes x
-// QUEUE float2), then the two half-lists of every query (2 x QPW x KP
-// float2), then positions / approximate values / exact distances
-// (3 x QPW x KP words).
+// Lanes l and l^32 hold sorted lists of the same query; both end with the
+// first KP of the union, sorted (a bitonic merge: the element-wise minimum of
+// one list and the other reversed holds the KP smallest, then half-cleaners).
 template <int KP>
-constexpr int scratch_bytes() { return (64 * QUEUE * 8 > QPW * KP * 16) ? 64 * QUEUE * 8 : QPW * KP * 16; }
-
-template <int KP, bool BF16>
-struct LeafShared {
-  uint32_t ids[KNNG_MAX_LEAF];
-  float nrm[KNNG_MAX_LEAF];
-  float tnorm[4][TILE];
-  float mu[BF16 ? MU_MAX : 1];
-  float red[8];
-  int flag;
-  alignas(16) unsigned char scratch[4][scratch_bytes<KP>()];
-};
-
-// Fragments: lane (h = lane/32, r = lane%32) owns features [h*HALF, h*HALF+HALF)
-// of each KC-wide chunk; MFMA step s uses feature h*HALF + s (FP32) or
-// h*HALF + 8 s .. +7 (BF16).  A and B use the same mapping, so the
-// contraction covers every feature exactly once.
-template <int KC, bool BF16>
-struct Frag {
-  static constexpr int HALF = KC / 2;
-  static constexpr int N4 = HALF / 4;
-  float4 f[N4];
-  __device__ __forceinline__ void load(const float* __restrict__ row, int kc, int d, int h, const float* mu, bool ok) {
+__device__ __forceinline__ void pair_merge(float (&v)[KP], int (&p)[KP]) {
+  float ov[KP];
+  int op[KP];
 #pragma unroll
-    for (int i = 0; i < N4; ++i) {
-      int c = kc + h * HALF + 4 * i;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (ok && c < d) {
-        v = ld4(row + c);
-        if (BF16) {
-          v.x -= mu[c]; v.y -= mu[c + 1]; v.z -= mu[c + 2]; v.w -= mu[c + 3];
-        }
+  for (int s = 0; s < KP; ++s) {
+    ov[s] = __shfl_xor(v[s], 32);
+    op[s] = __shfl_xor(p[s], 32);
+  }
+#pragma unroll
+  for (int s = 0; s < KP; ++s) {
+    float bv = ov[KP - 1 - s];
+    int bp = op[KP - 1 - s];
+    bool tb = vp_less(bv, bp, v[s], p[s]);
+    v[s] = tb ? bv : v[s];
+    p[s] = tb ? bp : p[s];
+  }
+#pragma unroll
+  for (int stride = KP / 2; stride > 0; stride >>= 1) {
+#pragma unroll
+    for (int s = 0; s < KP; ++s) {
+      if ((s & stride) == 0) {
+        bool sw = vp_less(v[s + stride], p[s + stride], v[s], p[s]);
+        float tv = v[s];
+        int tp = p[s];
+        v[s] = sw ? v[s + stride] : v[s];
+        p[s] = sw ? p[s + stride] : p[s];
+        v[s + stride] = sw ? tv : v[s + stride];
+        p[s + stride] = sw ? tp : p[s + stride];
       }
-      f[i] = v;
     }
   }
-};
+}
 
-template <int KC, bool BF16>
-__device__ __forceinline__ void gram_chunk(const Frag<KC, BF16>& a, const Frag<KC, BF16>& b, f32x16& acc0, f32x16& acc1) {
-  if constexpr (!BF16) {
+// Four canonical distances from one row to four rows (identical arithmetic
+// to dist2_g16 for each pair; the loads of all five rows are in flight together).
+__device__ __forceinline__ void dist2_g16_x4(const float* __restrict__ x, const float* const (&y)[4], int d, int g,
+                                             float (&out)[4]) {
+  float a[4][4];
 #pragma unroll
-    for (int i = 0; i < Frag<KC, BF16>::N4; ++i) {
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.f[i].x, b.f[i].x, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.f[i].y, b.f[i].y, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.f[i].z, b.f[i].z, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.f[i].w, b.f[i].w, acc1, 0, 0, 0);
-    }
-  } else {
+  for (int u = 0; u < 4; ++u) a[u][0] = a[u][1] = a[u][2] = a[u][3] = 0.f;
+  const int nc = d >> 2;
+  for (int c = g; c < nc; c += 16) {
+    float4 xv = ((const float4*)x)[c];
+    float4 w[4];
 #pragma unroll
-    for (int i = 0; i < Frag<KC, BF16>::N4; i += 2) {
-      bf16x8 av, bv;
-      av[0] = (__bf16)a.f[i].x; av[1] = (__bf16)a.f[i].y; av[2] = (__bf16)a.f[i].z; av[3] = (__bf16)a.f[i].w;
-      av[4] = (__bf16)a.f[i + 1].x; av[5] = (__bf16)a.f[i + 1].y; av[6] = (__bf16)a.f[i + 1].z; av[7] = (__bf16)a.f[i + 1].w;
-      bv[0] = (__bf16)b.f[i].x; bv[1] = (__bf16)b.f[i].y; bv[2] = (__bf16)b.f[i].z; bv[3] = (__bf16)b.f[i].w;
-      bv[4] = (__bf16)b.f[i + 1].x; bv[5] = (__bf16)b.f[i + 1].y; bv[6] = (__bf16)b.f[i + 1].z; bv[7] = (__bf16)b.f[i + 1].w;
-      if ((i / 2) % 2 == 0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc0, 0, 0, 0);
-      else acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc1, 0, 0, 0);
+    for (int u = 0; u < 4; ++u) w[u] = ((const float4*)y[u])[c];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      float e0 = xv.x - w[u].x, e1 = xv.y - w[u].y, e2 = xv.z - w[u].z, e3 = xv.w - w[u].w;
+      a[u][0] = __builtin_fmaf(e0, e0, a[u][0]);
+      a[u][1] = __builtin_fmaf(e1, e1, a[u][1]);
+      a[u][2] = __builtin_fmaf(e2, e2, a[u][2]);
+      a[u][3] = __builtin_fmaf(e3, e3, a[u][3]);
     }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    float s = (a[u][0] + a[u][1]) + (a[u][2] + a[u][3]);
+    s += __shfl_xor(s, 8, 16);
+    s += __shfl_xor(s, 4, 16);
+    s += __shfl_xor(s, 2, 16);
+    s += __shfl_xor(s, 1, 16);
+    out[u] = s;
   }
 }
 
 __device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; }
 
+// Tile element types: FP32 rows padded by 4 floats, BF16 rows by 8 halves;
+// either way consecutive rows start 16 bytes apart modulo the bank width.
+template <int KC, bool BF16>
+struct TileT {
+  static constexpr int STRIDE = BF16 ? (KC + 8) : (KC + 4);   // elements per row
+  using E = typename std::conditional<BF16, __bf16, float>::type;
+  E v[TILE * STRIDE];
+};
+
 template <int KC, int KP, bool BF16>
-__global__ __launch_bounds__(LEAF_THREADS) void k_leaf(LeafArgs a) {
+struct LeafShared {
+  uint32_t ids[KNNG_MAX_LEAF];
+  float nrm[KNNG_MAX_LEAF];
+  TileT<KC, BF16> tile[2];
+  float mu[BF16 ? MU_MAX : 1];
+  float red[8];
+  int flag;
+  // per wave: the tile loop's queues (64 x QUEUE float2), then the re-rank
+  // buffers (positions, approximate values, exact distances: 3 x QPW x KP)
+  alignas(16) unsigned char scratch[4][(64 * QUEUE * 8 > 12 * QPW * KP) ? 64 * QUEUE * 8 : 12 * QPW * KP];
+};
+
+// Query fragments in registers: lane (h, r) owns features [h*HALF, h*HALF+HALF)
+// of each KC-wide chunk; MFMA step s uses feature h*HALF + s (FP32) or
+// h*HALF + 8 s .. +7 (BF16).  Tiles use the same mapping for the candidates,
+// so the contraction covers every feature exactly once.
+template <int KC, bool BF16>
+struct QFrag {
+  static constexpr int HALF = KC / 2;
+  static constexpr int N4 = HALF / 4;
+  static constexpr int N8 = HALF / 8;
+  float4 f[BF16 ? 1 : N4];
+  bf16x8 b[BF16 ? N8 : 1];
+  __device__ __forceinline__ void load(const float* __restrict__ row, int kc, int d, int h, const float* mu, bool ok) {
+    if constexpr (!BF16) {
+#pragma unroll
+      for (int i = 0; i < N4; ++i) {
+        int c = kc + h * HALF + 4 * i;
+        f[i] = (ok && c < d) ? *(const float4*)(row + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < N8; ++i) {
+        int c = kc + h * HALF + 8 * i;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) b[i][e] = (__bf16)((ok && c + e < d) ? row[c + e] - mu[c + e] : 0.f);
+      }
+    }
+  }
+};
+
+template <int KC, int KP, bool BF16>
+__global__ __launch_bounds__(LEAF_THREADS, 2) void k_leaf(LeafArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  LeafShared<KP, BF16>& S = *reinterpret_cast<LeafShared<KP, BF16>*>(smem_raw);
+  using Sh = LeafShared<KC, KP, BF16>;
+  using Tile = TileT<KC, BF16>;
+  Sh& S = *reinterpret_cast<Sh*>(smem_raw);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, h = lane >> 5, r32 = lane & 31;
   const int d = a.d, k = a.k;
   const int64_t L = blockIdx.x;
@@ -153,10 +216,10 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(LeafArgs a) {
   }
   float my_max_n = 0.f, my_max_c = 0.f;
   int all_int = 1;
-  for (int i = tid; i < m; i += LEAF_THREADS) {
+  for (int i = w; i < m; i += 4) {            // a wave per member row, lanes over features
     const float* x = a.X + (size_t)S.ids[i] * d;
     float nacc = 0.f, cacc = 0.f;
-    for (int j = 0; j < d; ++j) {
+    for (int j = lane; j < d; j += 64) {
       float v = x[j];
       if (BF16) {
         float c = v - S.mu[j];
@@ -168,14 +231,14 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(LeafArgs a) {
         all_int &= (v == rintf(v));
       }
     }
+    for (int o = 32; o > 0; o >>= 1) {
+      nacc += __shfl_xor(nacc, o);
+      cacc += __shfl_xor(cacc, o);
+    }
     if (!BF16) all_int &= (nacc <= 4194304.0f);   // 2^22: every Gram partial sum exact
-    S.nrm[i] = nacc;
+    if (lane == 0) S.nrm[i] = nacc;
     my_max_n = fmaxf(my_max_n, nacc);
     my_max_c = fmaxf(my_max_c, cacc);
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    my_max_n = fmaxf(my_max_n, __shfl_xor(my_max_n, o));
-    my_max_c = fmaxf(my_max_c, __shfl_xor(my_max_c, o));
   }
   if (lane == 0) { S.red[w] = my_max_n; S.red[4 + w] = my_max_c; }
   if (!all_int) S.flag = 0;
@@ -187,103 +250,161 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf(LeafArgs a) {
 
   unsigned char* scr = S.scratch[w];
   float2* myq = reinterpret_cast<float2*>(scr) + lane * QUEUE;
+  constexpr int HALF = KC / 2;
+  constexpr int F4_PER_ROW = KC / 4;
+  constexpr int STAGE_F4 = TILE * F4_PER_ROW / LEAF_THREADS;   // float4 per thread per tile chunk
+  static_assert(STAGE_F4 >= 1, "tile too small for the block");
+  const int nchunk = (d + KC - 1) / KC;
+  const int ntile = (m + TILE - 1) / TILE;
+  const int nsteps = ntile * nchunk;
+
+  // global -> registers for step st (tile st / nchunk, chunk st % nchunk)
+  auto stage_load = [&](int st, float4 (&rg)[STAGE_F4]) {
+    int c0 = (st / nchunk) * TILE, kc = (st % nchunk) * KC;
+#pragma unroll
+    for (int u = 0; u < STAGE_F4; ++u) {
+      int e = tid + u * LEAF_THREADS;
+      int row = e / F4_PER_ROW, col = (e % F4_PER_ROW) * 4;
+      int cp = c0 + row;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (cp < m && kc + col < d) v = *(const float4*)(a.X + (size_t)S.ids[cp] * d + kc + col);
+      rg[u] = v;
+    }
+  };
+  auto stage_store = [&](int st, int buf, const float4 (&rg)[STAGE_F4]) {
+    int kc = (st % nchunk) * KC;
+#pragma unroll
+    for (int u = 0; u < STAGE_F4; ++u) {
+      int e = tid + u * LEAF_THREADS;
+      int row = e / F4_PER_ROW, col = (e % F4_PER_ROW) * 4;
+      if constexpr (!BF16) {
+        *(float4*)&S.tile[buf].v[row * Tile::STRIDE + col] = rg[u];
+      } else {
+        float4 v = rg[u];
+        bool in = kc + col < d;   // padded features stay exactly zero
+        __bf16* dst = &S.tile[buf].v[row * Tile::STRIDE + col];
+        dst[0] = (__bf16)(in ? v.x - S.mu[kc + col] : 0.f);
+        dst[1] = (__bf16)(in ? v.y - S.mu[kc + col + 1] : 0.f);
+        dst[2] = (__bf16)(in ? v.z - S.mu[kc + col + 2] : 0.f);
+        dst[3] = (__bf16)(in ? v.w - S.mu[kc + col + 3] : 0.f);
+      }
+    }
+  };
 
   for (int qb = 0; qb < m; qb += QPB) {
     const int qbase = qb + w * QPW;
-    if (qbase >= m) continue;                 // whole wave idle in this pass
+    const bool wave_on = qbase < m;           // uniform per wave
     const int qpos = qbase + r32;
     const bool qok = qpos < m;
     const float* qrow = a.X + (size_t)S.ids[qok ? qpos : 0] * d;
-    Frag<KC, BF16> qf, cf;
-    const bool one_chunk = d <= KC;
-    if (one_chunk) qf.load(qrow, 0, d, h, S.mu, qok);
+    QFrag<KC, BF16> qf;
+    if (nchunk == 1 && wave_on) qf.load(qrow, 0, d, h, S.mu, qok);
     float lv[KP];
     int lp[KP];
 #pragma unroll
     for (int s = 0; s < KP; ++s) { lv[s] = __int_as_float(0x7F800000); lp[s] = -1; }
     float thr_pair = __int_as_float(0x7F800000);
-    for (int c0 = 0; c0 < m; c0 += TILE) {
-      const int cpos = c0 + r32;
-      const bool cok = cpos < m;
-      const float* crow = a.X + (size_t)S.ids[cok ? cpos : 0] * d;
-      f32x16 acc0 = {0}, acc1 = {0};
-      for (int kc = 0; kc < d; kc += KC) {
-        if (!one_chunk) qf.load(qrow, kc, d, h, S.mu, qok);
-        cf.load(crow, kc, d, h, S.mu, cok);
-        gram_chunk<KC, BF16>(cf, qf, acc0, acc1);
-      }
-      if (lane < TILE) S.tnorm[w][lane] = (c0 + lane < m) ? S.nrm[c0 + lane] : 0.f;
-      wave_sync();
-      // filter this tile into the lane's queue
-      const float thr = fminf(lv[KP - 1], thr_pair);
-      int cnt = 0;
+    f32x16 acc0 = {0}, acc1 = {0};
+    {
+      float4 rg[STAGE_F4];
+      stage_load(0, rg);
+      stage_store(0, 0, rg);
+    }
+    __syncthreads();
+    for (int st = 0; st < nsteps; ++st) {
+      const int buf = st & 1;
+      const int c0 = (st / nchunk) * TILE, kci = st % nchunk;
+      float4 rg[STAGE_F4];
+      const bool more = st + 1 < nsteps;
+      if (more) stage_load(st + 1, rg);
+      if (wave_on) {
+        if (nchunk > 1) qf.load(qrow, kci * KC, d, h, S.mu, qok);
+        if (kci == 0) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        int ci = 8 * (r >> 2) + 4 * h + (r & 3);
-        int cp = c0 + ci;
-        float g = acc0[r] + acc1[r];
-        float sv = S.tnorm[w][ci] - 2.0f * g;
-        bool ok = qok && cp < m && cp != qpos && (sv < lv[KP - 1]) && (sv <= thr);
-        if (ok) myq[cnt] = make_float2(sv, __int_as_float(cp));
-        cnt += ok ? 1 : 0;
-      }
-      for (int q = 0; __any(q < cnt); ++q) {
-        if (q < cnt) {
-          float2 e = myq[q];
-          if (e.x < lv[KP - 1]) list_insert<KP>(lv, lp, e.x, __float_as_int(e.y));
+          for (int r = 0; r < 16; ++r) { acc0[r] = 0.f; acc1[r] = 0.f; }
+        }
+        if constexpr (!BF16) {
+          const float4* trow = reinterpret_cast<const float4*>(&S.tile[buf].v[r32 * Tile::STRIDE + h * HALF]);
+#pragma unroll
+          for (int i = 0; i < HALF / 4; ++i) {
+            float4 av = trow[i];
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, qf.f[i].x, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, qf.f[i].y, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, qf.f[i].z, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, qf.f[i].w, acc1, 0, 0, 0);
+          }
+        } else {
+          const bf16x8* trow = reinterpret_cast<const bf16x8*>(&S.tile[buf].v[r32 * Tile::STRIDE + h * HALF]);
+#pragma unroll
+          for (int i = 0; i < HALF / 8; ++i) {
+            bf16x8 av = trow[i];
+            if (i % 2 == 0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, qf.b[i], acc0, 0, 0, 0);
+            else acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, qf.b[i], acc1, 0, 0, 0);
+          }
+        }
+        if (kci == nchunk - 1) {
+          // filter this tile into the lane's queue, half a tile at a time
+#pragma unroll
+          for (int half = 0; half < 2; ++half) {
+            int cnt = 0;
+#pragma unroll
+            for (int rr = 0; rr < 8; ++rr) {
+              const int r = half * 8 + rr;
+              int ci = 8 * (r >> 2) + 4 * h + (r & 3);
+              int cp = c0 + ci;
+              float g = acc0[r] + acc1[r];
+              float sv = (cp < m ? S.nrm[cp] : 0.f) - 2.0f * g;
+              bool ok = qok && cp < m && cp != qpos && (sv < lv[KP - 1]) && (sv <= thr_pair);
+              if (ok) myq[cnt] = make_float2(sv, __int_as_float(cp));
+              cnt += ok ? 1 : 0;
+            }
+            for (int q = 0; __any(q < cnt); ++q) {
+              if (q < cnt) {
+                float2 e = myq[q];
+                if (e.x < lv[KP - 1]) list_insert<KP>(lv, lp, e.x, __float_as_int(e.y));
+              }
+            }
+          }
+          thr_pair = __shfl_xor(lv[KP - 1], 32);
         }
       }
-      thr_pair = __shfl_xor(lv[KP - 1], 32);
-      wave_sync();
+      if (more) stage_store(st + 1, buf ^ 1, rg);
+      __syncthreads();
     }
-    // ---- merge the two half-lists of each query
-    float2* LA = reinterpret_cast<float2*>(scr);
-    float2* LB = LA + QPW * KP;
-    {
-      float2* mine = h == 0 ? LA : LB;
-#pragma unroll
-      for (int s2 = 0; s2 < KP; ++s2) mine[r32 * KP + s2] = make_float2(lv[s2], __int_as_float(lp[s2]));
-    }
-    wave_sync();
-    float mv[KP];
-    int mp[KP];
-    if (h == 0) {
-      int ia = 0, ib = 0;
-#pragma unroll
-      for (int s2 = 0; s2 < KP; ++s2) {
-        float2 ea = LA[r32 * KP + (ia < KP ? ia : KP - 1)];
-        float2 eb = LB[r32 * KP + (ib < KP ? ib : KP - 1)];
-        float va = ia < KP ? ea.x : __int_as_float(0x7F800000);
-        float vb = ib < KP ? eb.x : __int_as_float(0x7F800000);
-        unsigned pa = ia < KP ? (unsigned)__float_as_int(ea.y) : 0xFFFFFFFFu;
-        unsigned pb2 = ib < KP ? (unsigned)__float_as_int(eb.y) : 0xFFFFFFFFu;
-        bool take_a = (va < vb) || (va == vb && pa <= pb2);
-        mv[s2] = take_a ? va : vb;
-        mp[s2] = (int)(take_a ? pa : pb2);
-        ia += take_a ? 1 : 0;
-        ib += take_a ? 0 : 1;
-      }
-    }
-    wave_sync();
-    int* pb = reinterpret_cast<int*>(scr);            // [QPW][KP] candidate positions
+    if (!wave_on) continue;                   // no barrier below this point
+    // ---- merge the two half-lists of each query (both lanes end with it)
+    pair_merge<KP>(lv, lp);
+    int* pb = reinterpret_cast<int*>(scr);                       // [QPW][KP] candidate positions
     float* vbuf = reinterpret_cast<float*>(scr) + QPW * KP;      // [QPW][KP] approximate values
     float* dex = reinterpret_cast<float*>(scr) + 2 * QPW * KP;   // [QPW][KP] exact distances
+    wave_sync();
     if (h == 0) {
 #pragma unroll
-      for (int s2 = 0; s2 < KP; ++s2) { pb[r32 * KP + s2] = mp[s2]; vbuf[r32 * KP + s2] = mv[s2]; }
+      for (int s2 = 0; s2 < KP; ++s2) { pb[r32 * KP + s2] = lp[s2]; vbuf[r32 * KP + s2] = lv[s2]; }
     }
     wave_sync();
-    // ---- exact re-rank: 4 (query, candidate) pairs per step, 16 lanes each
-    const int g = lane >> 4, gl = lane & 15;
-    for (int pr = g; pr < QPW * KP; pr += 4) {
-      int qj = pr / KP;
-      int cp = pb[pr];
-      int qp = qbase + qj;
-      bool ok = cp >= 0 && qp < m;
-      const float* xq = a.X + (size_t)S.ids[qp < m ? qp : 0] * d;
-      const float* xc = a.X + (size_t)S.ids[ok ? cp : 0] * d;
-      float dd = dist2_g16(xq, xc, d, gl);
-      if (gl == 0) dex[pr] = ok ? dd : __int_as_float(0x7F800000);
+    // ---- exact re-rank: groups of 16 lanes, four pairs of one query at a time
+    {
+      const int g = lane >> 4, gl = lane & 15;
+      for (int blk = 0; blk < QPW * KP; blk += 16) {
+        const int qj = blk / KP;
+        const int qp = qbase + qj;
+        const float* xq = a.X + (size_t)S.ids[qp < m ? qp : 0] * d;
+        const float* xc[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          int cp = pb[blk + g + 4 * u];
+          ok[u] = cp >= 0 && qp < m;
+          xc[u] = a.X + (size_t)S.ids[ok[u] ? cp : 0] * d;
+        }
+        float dd[4];
+        dist2_g16_x4(xq, xc, d, gl, dd);
+        if (gl == 0) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) dex[blk + g + 4 * u] = ok[u] ? dd[u] : __int_as_float(0x7F800000);
+        }
+      }
     }
     wave_sync();
     // ---- sort each query's KP (distance, id) keys; blocks of KP over the wave
@@ -411,7 +532,7 @@ __global__ __launch_bounds__(256) void k_leaf_exact(LeafArgs a) {
 
 template <int KC, int KP, bool BF16>
 hipError_t launch_leaf_t(const LeafArgs& a, hipStream_t s) {
-  size_t shm = sizeof(LeafShared<KP, BF16>);
+  size_t shm = sizeof(LeafShared<KC, KP, BF16>);
   auto kern = k_leaf<KC, KP, BF16>;
   static bool attr_set = false;
   if (!attr_set) {

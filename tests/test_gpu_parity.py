@@ -1,6 +1,7 @@
-"""GPU parity: each C-ABI entry point against the CPU oracle, stage by stage
-(the oracle stage is fed the GPU's previous-stage output, so an allowed tie
-swap cannot cascade), plus end-to-end runs, edge cases and determinism."""
+"""GPU parity: each C-ABI entry point against the CPU oracle, stage by stage,
+plus end-to-end runs, edge cases and determinism.  The oracle never consumes
+a GPU output: every oracle stage runs on the oracle's own previous stage (or
+on inputs the test itself draws), and the GPU chain runs on its own."""
 import sys
 import time
 
@@ -126,6 +127,40 @@ def test_divide_direction_override(dev):
     assert np.array_equal(perm_h, perm_o)
 
 
+@pytest.mark.parametrize("case", [("gauss", 20_000, 32, 256, 16), ("sift", 20_000, 128, 512, 16),
+                                  ("gist", 3_000, 960, 256, 8), ("gauss", 700, 8, 16, 30)],
+                         ids=lambda c: f"{c[0]}-n{c[1]}-d{c[2]}-it{c[4]}")
+def test_pca_divide(dev, case):
+    """Principal-direction split (Section 3.4): wherever the GPU tree and the
+    oracle tree hold the same node (same point set), the GPU's FP32
+    power-iteration direction agrees with the oracle's float64 one; the two
+    partitions agree except where a key near the median flips (the
+    partition given a direction is bit-exact: test_divide_direction_override)."""
+    kind, n, d, g, iters = case
+    say("pca divide", case)
+    X = _data(kind, n, d, 111)
+    kp, op = _params(n, d, 1, leaf_max=g, seed=7, split=K.SPLIT_PCA)
+    kp.pca_iters = iters
+    X_t = torch.from_numpy(X).to(dev)
+    _, _, perm_h, off_h, dirs = gpu_divide(kp, X_t, 0, dev, want_dirs=True)
+    perm_o, off_o, dirs_o = O.divide(X, op, 0, split="pca", pca_iters=iters)
+    levels, _ = O.tree_shape(op, 0)
+    nodes = [nd for lvl in levels for nd in sorted(lvl, key=lambda x: x[1])]
+    worst, compared = 1.0, 0
+    for i, (v, off0, m, left) in enumerate(nodes):
+        if not np.array_equal(np.sort(perm_h[off0:off0 + m]), np.sort(perm_o[off0:off0 + m])):
+            continue
+        c = float(dirs[i].astype(np.float64) @ dirs_o[v].astype(np.float64))
+        assert abs(np.linalg.norm(dirs[i]) - 1) < 1e-5
+        worst = min(worst, c)
+        compared += 1
+    same_leaves = np.mean([np.array_equal(np.sort(perm_h[a:b]), np.sort(perm_o[a:b])) for a, b in zip(off_h[:-1], off_h[1:])])
+    say(f"  nodes compared={compared}/{len(nodes)} worst cos={worst:.7f} identical leaves={same_leaves:.3f}")
+    assert compared >= 1 and nodes[0][0] == 1
+    assert worst >= 1 - 1e-4
+    assert same_leaves >= 0.9
+
+
 LEAF_CASES = [
     # kind, n, d, k, leaf_max, cyc, precision, rerank_m
     ("gauss", 10_000, 32, 10, 256, 0, K.FP32, 6),
@@ -155,8 +190,10 @@ def test_leaf_knn_parity(dev, case):
     t = 1
     perm, leaf_off, perm_h, off_h, _ = gpu_divide(kp, X_t, t, dev)
     _, _, gi, gd, diag = gpu_leaf(kp, X_t, perm, leaf_off, len(off_h) - 1, dev)
-    oi, od = O.leaf_knn(X, perm_h, off_h, k)
-    mem = leaf_members(perm_h, off_h)
+    perm_o, off_o, _ = O.divide(X, op, t)
+    assert np.array_equal(perm_h, perm_o)
+    oi, od = O.leaf_knn(X, perm_o, off_o, k)
+    mem = leaf_members(perm_o, off_o)
     rows = range(n)
     swaps = compare_rows(X, gi, gd, oi, rows, allowed=lambda i: mem[i])
     say(f"  swaps={swaps} fallback_rows={diag['leaf_rows_fallback']} of {diag['leaf_rows']}")
@@ -196,12 +233,20 @@ MERGE_CASES = [("gauss", 10_000, 32, 10, 256, 4), ("sift", 20_000, 128, 10, 512,
                ("dup", 2_000, 16, 10, 30, 2), ("gist", 3_000, 960, 20, 256, 3)]
 
 
+def _oracle_lists(X, op, T):
+    lists = []
+    for t in range(T):
+        perm_o, off_o, _ = O.divide(X, op, t)
+        lists.append(O.leaf_knn(X, perm_o, off_o, op.k)[0])
+    return lists
+
+
 @pytest.mark.parametrize("case", MERGE_CASES, ids=lambda c: f"{c[0]}-n{c[1]}-T{c[5]}")
 def test_merge_parity(dev, case):
     kind, n, d, k, g, T = case
     say("merge", case)
     X = _data(kind, n, d, 51)
-    kp, _ = _params(n, d, k, T=T, leaf_max=g, seed=9)
+    kp, op = _params(n, d, k, T=T, leaf_max=g, seed=9)
     X_t = torch.from_numpy(X).to(dev)
     Li, Ld = _lists_from_gpu(kp, X_t, dev, T)
     out_i = torch.empty((n, k), dtype=torch.int32, device=dev)
@@ -209,9 +254,9 @@ def test_merge_parity(dev, case):
     K.merge(kp, T, Li, Ld, out_i, out_d)
     torch.cuda.synchronize()
     gi, gd = out_i.cpu().numpy().view(np.uint32), out_d.cpu().numpy()
-    lists_h = [Li[t].cpu().numpy().view(np.uint32) for t in range(T)]
-    oi, od = O.merge(X, lists_h, k)
-    union = lambda i: set(int(x) for t in range(T) for x in lists_h[t][i] if x != NONE)
+    lists_o = _oracle_lists(X, op, T)
+    oi, od = O.merge(X, lists_o, k)
+    union = lambda i: set(int(x) for t in range(T) for x in lists_o[t][i] if x != NONE)
     swaps = compare_rows(X, gi, gd, oi, range(n), allowed=union)
     if kind == "sift":
         assert swaps == 0 and np.array_equal(gi, oi)
@@ -228,7 +273,7 @@ def test_propagate_round_parity(dev, case):
     kind, n, d, k, g, T, pw = case
     say("propagate", case)
     X = _data(kind, n, d, 61)
-    kp, _ = _params(n, d, k, T=T, leaf_max=g, pairwise=pw, seed=4)
+    kp, op = _params(n, d, k, T=T, leaf_max=g, pairwise=pw, seed=4)
     X_t = torch.from_numpy(X).to(dev)
     Li, Ld = _lists_from_gpu(kp, X_t, dev, T)
     ids = torch.empty((n, k), dtype=torch.int32, device=dev)
@@ -237,14 +282,19 @@ def test_propagate_round_parity(dev, case):
     torch.cuda.synchronize()
     in_ids = ids.cpu().numpy().view(np.uint32).copy()
     in_d = dist.cpu().numpy().copy()
+    o_in, _ = O.merge(X, _oracle_lists(X, op, T), k)
+    same_input = int((o_in != in_ids).any(axis=1).sum())
     ws = K.alloc_workspace(kp, K.OP_PROPAGATE, dev)
     K.propagate(kp, X_t, ids, dist, 1, ws)
     torch.cuda.synchronize()
     diag = K.read_diag(kp, ws, K.OP_PROPAGATE)
     gi, gd = ids.cpu().numpy().view(np.uint32), dist.cpu().numpy()
-    oi, od, U = O.propagate_round(X, in_ids, k, bool(pw))
+    oi, od, U = O.propagate_round(X, o_in, k, bool(pw))
+    say(f"  rows whose merged input differs (tie swaps upstream): {same_input}")
+    assert same_input <= n // 1000
     swaps = compare_rows(X, gi, gd, oi, range(n))
-    assert diag["prop_candidates"] == int(U.sum())
+    if same_input == 0:
+        assert diag["prop_candidates"] == int(U.sum())
     # the k-th distance never increases
     valid = in_ids[:, -1] != NONE
     assert np.all(gd[valid, -1] <= in_d[valid, -1])
