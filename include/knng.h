@@ -172,15 +172,18 @@ int knng_merge(const knng_params* p, int n_lists, const uint32_t* ids_in, const 
 int knng_propagate(const knng_params* p, const float* X, uint32_t* ids, float* dist, int rounds, void* ws,
                    size_t ws_bytes, void* stream);
 
-/* The whole method: p->T divisions, leaf k-NN per division, merge,
- * p->rounds propagation rounds.  ids, dist (n x k) receive the graph.      */
+/* The whole method: p->T divisions (advanced level by level together),
+ * leaf k-NN of every leaf of every division in one persistent launch
+ * (largest leaves first), merge, p->rounds propagation rounds.
+ * ids, dist (n x k) receive the graph.                                     */
 int knng_build(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
                void* stream);
 
 /* knng_build with a HIP event at every stage boundary; waits for the stream
- * at the end.  ms_out (host, at least 2T + 1 + rounds entries) receives the
- * GPU time of: divide t (entries 2t), leaf k-NN t (2t + 1) for t < T, the
- * merge (2T), then each propagation round (2T + 1 + r).                    */
+ * at the end.  ms_out (host, at least 3 + rounds entries) receives the GPU
+ * time of: all T divisions (entry 0, the batched divide launches), the leaf
+ * k-NN of every leaf of every division (1, one persistent launch plus its
+ * exact-row pass), the merge (2), then each propagation round (3 + r).     */
 int knng_build_timed(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
                      void* stream, float* ms_out, int ms_cap);
 

@@ -179,12 +179,12 @@ def build(p: Params, X, ids, dist, ws, stream=None):
 def build_timed(p: Params, X, ids, dist, ws, stream=None) -> dict:
     """knng_build with per-stage GPU times (ms); waits for the stream."""
     cp = p.c()
-    nst = 2 * p.T + 1 + p.rounds
+    nst = 3 + p.rounds
     buf = (ctypes.c_float * nst)()
     _check(_lib.knng_build_timed(ctypes.byref(cp), _ptr(X), _ptr(ids), _ptr(dist), _ptr(ws),
                                  ws.numel() * ws.element_size(), _stream(stream), buf, nst))
     v = list(buf)
-    return {"divide": v[0:2 * p.T:2], "leaf": v[1:2 * p.T:2], "merge": v[2 * p.T], "rounds": v[2 * p.T + 1:]}
+    return {"divide": v[0], "leaf": v[1], "merge": v[2], "rounds": v[3:]}
 
 
 def read_diag(p: Params, ws, op: int, stream=None) -> dict:

@@ -83,7 +83,7 @@ __device__ void load_direction(const DivideLevelArgs& a, const SegDesc& sd, floa
     float v;
     if (a.dirs) v = a.dirs[(size_t)sd.dir_index * a.d + j];
     else if (a.pca_iters > 0) v = a.pca_dirs[(size_t)sd.dir_index * a.d + j];
-    else v = rp_entry(a.seed, (uint32_t)a.t, sd.v, (uint32_t)j);
+    else v = rp_entry(a.seed, sd.t, sd.v, (uint32_t)j);
     dir[j] = v;
     if (a.dirs_out && first_item) a.dirs_out[(size_t)sd.dir_index * a.d + j] = v;
   }
@@ -117,8 +117,9 @@ __global__ __launch_bounds__(DIV_THREADS) void k_proj_hist0(DivideLevelArgs a) {
   const SegDesc sd = a.segs[it.seg];
   for (int b = threadIdx.x; b < (int)HIST_B0; b += DIV_THREADS) lh[b] = 0;
   load_direction(a, sd, dir, it.start == sd.off);
+  const size_t base = (size_t)it.slot * (size_t)a.n;
   for (uint32_t i = threadIdx.x; i < it.len; i += DIV_THREADS) {
-    uint32_t pos = it.start + i;
+    size_t pos = base + it.start + i;
     uint32_t row = a.perm_in[pos];
     float key = dot_seq(a.X + (size_t)row * a.d, dir, a.d);
     uint32_t uk = ordered_key(key);
@@ -142,8 +143,9 @@ __global__ __launch_bounds__(DIV_THREADS) void k_hist_pass(DivideLevelArgs a, in
   for (int b = threadIdx.x; b < nb; b += DIV_THREADS) lh[b] = 0;
   __syncthreads();
   int shift_pre = pass == 1 ? 21 : 10;
+  const uint32_t* uks = a.ukeys + (size_t)it.slot * (size_t)a.n + it.start;
   for (uint32_t i = threadIdx.x; i < it.len; i += DIV_THREADS) {
-    uint32_t uk = a.ukeys[it.start + i];
+    uint32_t uk = uks[i];
     if ((uk >> shift_pre) == prefix) {
       uint32_t dg = pass == 1 ? ((uk >> 10) & 0x7FF) : (uk & 0x3FF);
       atomicAdd(&lh[dg], 1u);
@@ -162,8 +164,9 @@ __global__ __launch_bounds__(DIV_THREADS) void k_part_count(DivideLevelArgs a) {
   uint32_t pivot, need;
   resolve(a.hist, it.seg, sd.left, 3, &pivot, &need, sh);
   int nl = 0, ne = 0;
+  const uint32_t* uks = a.ukeys + (size_t)it.slot * (size_t)a.n + it.start;
   for (uint32_t i = threadIdx.x; i < it.len; i += DIV_THREADS) {
-    uint32_t uk = a.ukeys[it.start + i];
+    uint32_t uk = uks[i];
     nl += uk < pivot;
     ne += uk == pivot;
   }
@@ -179,8 +182,11 @@ __global__ __launch_bounds__(DIV_THREADS) void k_part_count(DivideLevelArgs a) {
 __global__ __launch_bounds__(DIV_THREADS) void k_part_scatter(DivideLevelArgs a) {
   __shared__ int sh[16];
   const ItemDesc it = a.items[blockIdx.x];
+  const size_t base = (size_t)it.slot * (size_t)a.n;
+  const uint32_t* pin = a.perm_in + base;
+  uint32_t* pout = a.perm_out + base;
   if (it.seg == 0xFFFFFFFFu) {   // positions outside this level's internal nodes
-    for (uint32_t i = threadIdx.x; i < it.len; i += DIV_THREADS) a.perm_out[it.start + i] = a.perm_in[it.start + i];
+    for (uint32_t i = threadIdx.x; i < it.len; i += DIV_THREADS) pout[it.start + i] = pin[it.start + i];
     return;
   }
   const SegDesc sd = a.segs[it.seg];
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(DIV_THREADS) void k_part_scatter(DivideLevelArgs a)
   for (uint32_t t0 = 0; t0 < it.len; t0 += DIV_THREADS) {
     uint32_t i = t0 + threadIdx.x;
     bool valid = i < it.len;
-    uint32_t uk = valid ? a.ukeys[it.start + i] : 0xFFFFFFFFu;
+    uint32_t uk = valid ? a.ukeys[base + it.start + i] : 0xFFFFFFFFu;
     int isl = valid && uk < pivot, ise = valid && uk == pivot;
     int tl, te;
     int rl = block_excl_scan(isl, sh, &tl);
@@ -217,7 +223,7 @@ __global__ __launch_bounds__(DIV_THREADS) void k_part_scatter(DivideLevelArgs a)
         uint32_t lbefore = nless + (neq < need ? neq : need);
         dest = sd.off + sd.left + (idx - lbefore);
       }
-      a.perm_out[dest] = a.perm_in[it.start + i];
+      pout[dest] = pin[it.start + i];
     }
     less_before += tl;
     eq_before += te;
@@ -251,10 +257,10 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_dirs(DivideLevelArgs a) {
   if (wd < 1) wd = 1;
   if (threadIdx.x < s) {
     uint32_t pos = (uint32_t)(((uint64_t)threadIdx.x * m) / s) +
-                   (uint32_t)(rand64(a.seed, TAG_SAMPLE, (uint32_t)a.t, sd.v, threadIdx.x) % wd);
-    rows[threadIdx.x] = a.perm_in[sd.off + pos];
+                   (uint32_t)(rand64(a.seed, TAG_SAMPLE, sd.t, sd.v, threadIdx.x) % wd);
+    rows[threadIdx.x] = a.perm_in[(size_t)sd.slot * (size_t)a.n + sd.off + pos];
   }
-  for (int j = threadIdx.x; j < d; j += DIV_THREADS) v[j] = rp_entry(a.seed, (uint32_t)a.t, sd.v, (uint32_t)j);
+  for (int j = threadIdx.x; j < d; j += DIV_THREADS) v[j] = rp_entry(a.seed, sd.t, sd.v, (uint32_t)j);
   __syncthreads();
   if constexpr (SAMPLE_LDS) {
     // raw sample -> LDS: element e = (row, float4 column), 8 loads in flight per thread
@@ -373,10 +379,12 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t value, size_t count) {
   for (; i < count; i += stride) p[i] = value;
 }
 
-__global__ void k_iota(uint32_t* p, uint32_t n) {
+// slots consecutive copies of 0..n-1
+__global__ void k_iota(uint32_t* p, uint32_t n, uint32_t slots) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) p[i] = (uint32_t)i;
+  size_t tot = (size_t)n * slots;
+  for (; i < tot; i += stride) p[i] = (uint32_t)(i % n);
 }
 
 }  // namespace
@@ -389,10 +397,10 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_iota(uint32_t* p, uint32_t n, hipStream_t s) {
-  size_t blocks = ((size_t)n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_iota, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+hipError_t launch_iota(uint32_t* p, uint32_t n, uint32_t slots, hipStream_t s) {
+  size_t blocks = ((size_t)n * slots + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_iota, dim3((unsigned)blocks), dim3(256), 0, s, p, n, slots);
   return hipGetLastError();
 }
 

@@ -57,6 +57,14 @@ __global__ __launch_bounds__(256) void k_merge(int64_t n, int k, int n_lists, co
 }
 
 // ---------------------------------------------------------------- propagation, forward part
+// Blocks are dealt to the 8 XCDs round-robin; remapping block b to a
+// contiguous range per XCD keeps the points one XCD works on (and so the
+// candidate rows its L2 holds) neighbours in the visiting order.
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t nb) {
+  uint32_t q = nb / 8, r = nb % 8, x = b % 8, j = b / 8;
+  return x * q + (x < r ? x : r) + j;
+}
+
 // Wave per point p:
 //   1. C_p = ids of N(q) for q in N(p), sorted, duplicates, p and N(p) dropped;
 //   2. score every candidate with the canonical distance (16 lanes each);
@@ -68,8 +76,9 @@ __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
   __shared__ uint32_t cand_s[4][64 * R1];
   __shared__ float cd_s[4][64 * R1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t p = (int64_t)blockIdx.x * 4 + w;
-  if (p >= a.n) return;
+  const int64_t vis = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * 4 + w;
+  if (vis >= a.n) return;
+  const int64_t p = a.order ? (int64_t)a.order[vis] : vis;   // points in spatial order
   const int k = a.k, d = a.d;
   uint32_t nb = lane < k ? a.ids_in[(size_t)p * k + lane] : KNNG_NONE;
   float nbd = lane < k ? a.dist_in[(size_t)p * k + lane] : __int_as_float(0x7F800000);
@@ -251,8 +260,15 @@ __global__ __launch_bounds__(256) void k_prop_final(PropArgs a) {
   const int64_t p = (int64_t)blockIdx.x * 4 + w;
   if (p >= a.n) return;
   const int k = a.k;
-  uint64_t keep = lane < k ? pack_did(a.fwd_dist[(size_t)p * k + lane], a.fwd_ids[(size_t)p * k + lane]) : ~0ull;
   const uint32_t b0 = a.offs[p], b1 = a.offs[p + 1];
+  if (b0 == b1) {   // no proposals for p: its forward list is final
+    if (lane < k) {
+      a.ids_out[(size_t)p * k + lane] = a.fwd_ids[(size_t)p * k + lane];
+      a.dist_out[(size_t)p * k + lane] = a.fwd_dist[(size_t)p * k + lane];
+    }
+    return;
+  }
+  uint64_t keep = lane < k ? pack_did(a.fwd_dist[(size_t)p * k + lane], a.fwd_ids[(size_t)p * k + lane]) : ~0ull;
   const uint32_t chunk = 64 * (R - 1);   // register 0 carries the kept list
   uint32_t pos = b0;
   do {
@@ -353,7 +369,7 @@ hipError_t launch_propagate_round(const PropArgs& a, hipStream_t s) {
   unsigned blocks = (unsigned)((a.n + 3) / 4);
   hipLaunchKernelGGL(k_prop_scatter, dim3(blocks), dim3(256), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (a.k <= 64) hipLaunchKernelGGL(k_prop_final<4>, dim3(blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_prop_final<2>, dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

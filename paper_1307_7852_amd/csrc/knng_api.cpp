@@ -91,49 +91,181 @@ PlanPtr get_plan(const knng_params& p, int t, int* status) {
   return pl;
 }
 
-// ------------------------------------------------------------------ workspace layouts
-struct DivideLayout {
-  size_t diag, plan, perm_tmp, ukeys, hist, chunk, pca, total;
-  size_t plan_bytes;
+// ------------------------------------------------------------------ batched plans
+// A batch runs several divisions level by level: level l of the batch holds
+// every division's internal nodes at depth l (each tagged with its division
+// t and buffer slot), their split items, and copy items for every position
+// that is not inside a level-l internal node.  The leaf work list holds every
+// leaf of every division, largest first (longest-processing-time order for
+// the persistent leaf launch).
+struct Batch {
+  int64_t n = 0;
+  int slots = 0;
+  int depth = 0;
+  std::vector<SegDesc> segs;
+  std::vector<ItemDesc> items;
+  std::vector<LevelPlan> levels;
+  std::vector<LeafWork> work;
+  std::vector<int64_t> leaf_off0;   // leaf offsets of slot 0
+  uint32_t n_dirs = 0;              // direction rows: internal nodes of all slots
+  uint32_t max_segs = 0, max_items = 0;
+  size_t off_items = 0, off_work = 0, off_leaf = 0;
+  std::vector<char> blob;           // device image: segs | items | work | leaf_off0
 };
+using BatchPtr = std::shared_ptr<const Batch>;
 
-// Device copy of a plan: segments, items, then the leaf offsets (int64).
-size_t plan_blob_bytes(const Plan& pl) {
-  return pl.segs.size() * sizeof(SegDesc) + pl.items.size() * sizeof(ItemDesc) + pl.leaf_off.size() * 8;
-}
-size_t plan_leaf_off_offset(const Plan& pl) {
-  return pl.segs.size() * sizeof(SegDesc) + pl.items.size() * sizeof(ItemDesc);
-}
+struct BatchKey {
+  int64_t n; int32_t lm, cyc, qlo, qhi; uint64_t seed; std::vector<int> ts;
+  bool operator<(const BatchKey& o) const {
+    return std::tie(n, lm, cyc, qlo, qhi, seed, ts) < std::tie(o.n, o.lm, o.cyc, o.qlo, o.qhi, o.seed, o.ts);
+  }
+};
+std::mutex g_batch_mu;
+std::map<BatchKey, BatchPtr> g_batches;
 
-int divide_layout(const knng_params& p, int t_lo, int t_hi, DivideLayout& L) {
-  size_t plan_bytes = 0, max_segs = 0, max_items = 0, max_int = 0;
-  for (int t = t_lo; t < t_hi; ++t) {
-    int st;
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int make_batch(const knng_params& p, const std::vector<int>& ts, Batch& B) {
+  std::vector<PlanPtr> plans;
+  int st;
+  for (int t : ts) {
     PlanPtr pl = get_plan(p, t, &st);
     if (!pl) return st;
-    plan_bytes = std::max(plan_bytes, plan_blob_bytes(*pl));
-    max_segs = std::max<size_t>(max_segs, pl->max_level_segs());
-    max_items = std::max<size_t>(max_items, pl->max_level_items());
-    max_int = std::max<size_t>(max_int, pl->segs.size());
+    plans.push_back(pl);
   }
-  Carve c;
-  L.diag = c.take(sizeof(DiagDev));
-  L.plan = c.take(plan_bytes + 16);
-  L.perm_tmp = c.take((size_t)p.n * 4);
-  L.ukeys = c.take((size_t)p.n * 4);
-  L.hist = c.take(std::max<size_t>(1, max_segs) * HIST_TOTAL * 4);
-  L.chunk = c.take(std::max<size_t>(1, max_items) * 2 * 4);
-  L.pca = c.take(p.split == KNNG_SPLIT_PCA ? std::max<size_t>(1, max_int) * p.d * 4 : 0);
-  L.total = c.off;
-  L.plan_bytes = plan_bytes;
+  B = Batch();
+  B.n = p.n;
+  B.slots = (int)ts.size();
+  std::vector<uint32_t> dir_base(ts.size(), 0);
+  for (size_t b = 0; b < ts.size(); ++b) {
+    B.depth = std::max(B.depth, plans[b]->depth);
+    dir_base[b] = B.n_dirs;
+    B.n_dirs += (uint32_t)plans[b]->segs.size();
+  }
+  for (int l = 0; l < B.depth; ++l) {
+    LevelPlan lv{};
+    lv.seg_begin = (uint32_t)B.segs.size();
+    lv.item_begin = (uint32_t)B.items.size();
+    std::vector<ItemDesc> split, copy;
+    uint32_t nseg = 0;
+    for (size_t b = 0; b < ts.size(); ++b) {
+      const Plan& pl = *plans[b];
+      if (l < pl.depth) {
+        const LevelPlan& pv = pl.levels[l];
+        uint32_t item_base = (uint32_t)split.size();
+        for (uint32_t s2 = 0; s2 < pv.n_segs; ++s2) {
+          SegDesc sd = pl.segs[pv.seg_begin + s2];
+          sd.first_item += item_base;
+          sd.dir_index += dir_base[b];
+          sd.t = (uint32_t)ts[b];
+          sd.slot = (uint32_t)b;
+          B.segs.push_back(sd);
+          lv.max_seg = std::max(lv.max_seg, sd.m);
+        }
+        for (uint32_t i = 0; i < pv.n_items; ++i) {
+          ItemDesc it = pl.items[pv.item_begin + i];
+          it.slot = (uint32_t)b;
+          if (i < pv.n_split) {
+            it.seg += nseg;
+            split.push_back(it);
+          } else {
+            copy.push_back(it);
+          }
+        }
+        nseg += pv.n_segs;
+      } else {
+        for (int64_t c = 0; c < p.n; c += DIV_CHUNK)
+          copy.push_back({0xFFFFFFFFu, (uint32_t)c, (uint32_t)std::min<int64_t>(DIV_CHUNK, p.n - c), (uint32_t)b});
+      }
+    }
+    lv.n_segs = nseg;
+    lv.n_split = (uint32_t)split.size();
+    lv.n_items = (uint32_t)(split.size() + copy.size());
+    B.items.insert(B.items.end(), split.begin(), split.end());
+    B.items.insert(B.items.end(), copy.begin(), copy.end());
+    B.levels.push_back(lv);
+    B.max_segs = std::max(B.max_segs, lv.n_segs);
+    B.max_items = std::max(B.max_items, lv.n_items);
+  }
+  for (size_t b = 0; b < ts.size(); ++b) {
+    const std::vector<int64_t>& off = plans[b]->leaf_off;
+    for (size_t L = 0; L + 1 < off.size(); ++L)
+      B.work.push_back({(uint32_t)b, (uint32_t)(off[L + 1] - off[L]), (uint64_t)off[L]});
+  }
+  std::stable_sort(B.work.begin(), B.work.end(), [](const LeafWork& x, const LeafWork& y) { return x.m > y.m; });
+  B.leaf_off0 = plans[0]->leaf_off;
+  size_t a1 = align256(B.segs.size() * sizeof(SegDesc));
+  size_t a2 = align256(B.items.size() * sizeof(ItemDesc));
+  size_t a3 = align256(B.work.size() * sizeof(LeafWork));
+  size_t a4 = align256(B.leaf_off0.size() * 8);
+  B.off_items = a1;
+  B.off_work = a1 + a2;
+  B.off_leaf = a1 + a2 + a3;
+  B.blob.assign(a1 + a2 + a3 + a4, 0);
+  if (!B.segs.empty()) memcpy(B.blob.data(), B.segs.data(), B.segs.size() * sizeof(SegDesc));
+  if (!B.items.empty()) memcpy(B.blob.data() + B.off_items, B.items.data(), B.items.size() * sizeof(ItemDesc));
+  if (!B.work.empty()) memcpy(B.blob.data() + B.off_work, B.work.data(), B.work.size() * sizeof(LeafWork));
+  memcpy(B.blob.data() + B.off_leaf, B.leaf_off0.data(), B.leaf_off0.size() * 8);
   return KNNG_OK;
 }
 
-struct LeafLayout { size_t diag, fallback, total; };
-LeafLayout leaf_layout(const knng_params& p) {
+BatchPtr get_batch(const knng_params& p, const std::vector<int>& ts, int* status) {
+  BatchKey key{p.n, p.leaf_max, p.leaf_cap_cycle, p.q_lo_pm, p.q_hi_pm, p.seed, ts};
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    auto it = g_batches.find(key);
+    if (it != g_batches.end()) { *status = KNNG_OK; return it->second; }
+  }
+  auto B = std::make_shared<Batch>();
+  *status = make_batch(p, ts, *B);
+  if (*status != KNNG_OK) return nullptr;
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  if (g_batches.size() > 64) g_batches.clear();   // callers hold their own references
+  g_batches[key] = B;
+  return B;
+}
+
+std::vector<int> all_divisions(const knng_params& p) {
+  std::vector<int> ts(p.T);
+  for (int t = 0; t < p.T; ++t) ts[t] = t;
+  return ts;
+}
+
+// ------------------------------------------------------------------ workspace layouts
+// Scratch of the divide kernels for a batch (offsets relative to its base).
+struct DivScratch { size_t ukeys, hist, chunk, pca, total; };
+DivScratch div_scratch(const knng_params& p, const Batch& B) {
+  DivScratch L; Carve c;
+  L.ukeys = c.take((size_t)B.slots * p.n * 4);
+  L.hist = c.take(std::max<uint32_t>(1, B.max_segs) * (size_t)HIST_TOTAL * 4);
+  L.chunk = c.take(std::max<uint32_t>(1, B.max_items) * (size_t)2 * 4);
+  L.pca = c.take(p.split == KNNG_SPLIT_PCA ? std::max<uint32_t>(1, B.n_dirs) * (size_t)p.d * 4 : 0);
+  L.total = c.off;
+  return L;
+}
+
+// knng_divide: diag | plan blob | second permutation buffer | divide scratch
+struct DivideLayout { size_t diag, blob, tmp, scratch, total; };
+int divide_layout(const knng_params& p, int t, DivideLayout& L) {
+  int st;
+  BatchPtr B = get_batch(p, {t}, &st);
+  if (!B) return st;
+  Carve c;
+  L.diag = c.take(sizeof(DiagDev));
+  L.blob = c.take(B->blob.size());
+  L.tmp = c.take((size_t)p.n * 4);
+  L.scratch = c.take(div_scratch(p, *B).total);
+  L.total = c.off;
+  return KNNG_OK;
+}
+
+// leaf scratch: fallback list + work counter
+struct LeafLayout { size_t diag, fallback, counter, total; };
+LeafLayout leaf_layout(const knng_params& p, int slots) {
   LeafLayout L; Carve c;
   L.diag = c.take(sizeof(DiagDev));
-  L.fallback = c.take((size_t)p.n * 2 * 4);
+  L.fallback = c.take((size_t)slots * p.n * 2 * 4);
+  L.counter = c.take(64);
   L.total = c.off;
   return L;
 }
@@ -158,56 +290,62 @@ PropLayout prop_layout(const knng_params& p) {
   return L;
 }
 
-struct BuildLayout { size_t diag, lists_ids, lists_dist, perm, leaf_off, plans, sub, total; size_t plans_bytes; int64_t max_leaves; };
+// knng_build: diag | plan blob | T lists | two T-slot permutation buffers |
+// one region shared in turn by the divide, leaf and propagation scratch
+struct BuildLayout { size_t diag, blob, lists_ids, lists_dist, permA, permB, shared, total; };
 int build_layout(const knng_params& p, BuildLayout& L) {
-  DivideLayout D;
-  int st = divide_layout(p, 0, p.T, D);
-  if (st) return st;
-  size_t plans_bytes = 0;
-  int64_t max_leaves = 0;
-  for (int t = 0; t < p.T; ++t) {
-    PlanPtr pl = get_plan(p, t, &st);
-    if (!pl) return st;
-    plans_bytes += (plan_blob_bytes(*pl) + 255) & ~(size_t)255;
-    max_leaves = std::max(max_leaves, pl->n_leaves());
-  }
+  int st;
+  BatchPtr B = get_batch(p, all_divisions(p), &st);
+  if (!B) return st;
   size_t nk = (size_t)p.n * p.k;
   Carve c;
   L.diag = c.take(sizeof(DiagDev));
+  L.blob = c.take(B->blob.size());
   L.lists_ids = c.take(nk * 4 * p.T);
   L.lists_dist = c.take(nk * 4 * p.T);
-  L.perm = c.take((size_t)p.n * 4);
-  L.leaf_off = c.take(((size_t)max_leaves + 1) * 8);
-  L.plans = c.take(plans_bytes);
-  size_t sub = std::max({D.total, leaf_layout(p).total, prop_layout(p).total});
-  L.sub = c.take(sub);
+  L.permA = c.take((size_t)p.n * 4 * p.T);
+  L.permB = c.take((size_t)p.n * 4 * p.T);
+  size_t sh = std::max({div_scratch(p, *B).total, leaf_layout(p, p.T).total, prop_layout(p).total});
+  L.shared = c.take(sh);
   L.total = c.off;
-  L.plans_bytes = plans_bytes;
-  L.max_leaves = max_leaves;
   return KNNG_OK;
 }
 
-// ------------------------------------------------------------------ divide core
-// Runs every level of division t with the plan already resident at plan_dev.
-int divide_core(const knng_params& p, int t, const Plan& pl, const void* plan_dev, const float* X,
-                const float* dir_override, float* dirs_out, uint32_t* perm, int64_t* leaf_off_dev, char* ws,
-                const DivideLayout& L, hipStream_t s) {
-  uint32_t* tmp = (uint32_t*)(ws + L.perm_tmp);
-  uint32_t* ukeys = (uint32_t*)(ws + L.ukeys);
-  uint32_t* hist = (uint32_t*)(ws + L.hist);
-  uint32_t* chunk = (uint32_t*)(ws + L.chunk);
-  float* pca = p.split == KNNG_SPLIT_PCA ? (float*)(ws + L.pca) : nullptr;
-  const SegDesc* segs = (const SegDesc*)plan_dev;
-  const ItemDesc* items = (const ItemDesc*)((const char*)plan_dev + pl.segs.size() * sizeof(SegDesc));
-  int D = pl.depth;
-  uint32_t* buf[2];
-  buf[0] = (D % 2 == 0) ? perm : tmp;
-  buf[1] = (D % 2 == 0) ? tmp : perm;
-  HIP_TRY(launch_iota(buf[0], (uint32_t)p.n, s));
-  for (int l = 0; l < D; ++l) {
-    const LevelPlan& lv = pl.levels[l];
+hipError_t zero_diag(void* diag, hipStream_t s) {
+  return launch_fill_u32((uint32_t*)diag, 0u, sizeof(DiagDev) / 4, s);
+}
+
+int cu_count() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+// ------------------------------------------------------------------ stage cores
+// Runs every level of a batch of divisions with the batch's plan resident at
+// blob_dev.  buf[0] receives the identity; the final permutations land in
+// buf[depth % 2].
+int divide_core(const knng_params& p, const Batch& B, const char* blob_dev, const float* X, const float* dir_override,
+                float* dirs_out, uint32_t* buf0, uint32_t* buf1, char* scratch, hipStream_t s) {
+  DivScratch L = div_scratch(p, B);
+  uint32_t* ukeys = (uint32_t*)(scratch + L.ukeys);
+  uint32_t* hist = (uint32_t*)(scratch + L.hist);
+  uint32_t* chunk = (uint32_t*)(scratch + L.chunk);
+  float* pca = p.split == KNNG_SPLIT_PCA ? (float*)(scratch + L.pca) : nullptr;
+  const SegDesc* segs = (const SegDesc*)blob_dev;
+  const ItemDesc* items = (const ItemDesc*)(blob_dev + B.off_items);
+  uint32_t* buf[2] = {buf0, buf1};
+  HIP_TRY(launch_iota(buf[0], (uint32_t)p.n, (uint32_t)B.slots, s));
+  for (int l = 0; l < B.depth; ++l) {
+    const LevelPlan& lv = B.levels[l];
     DivideLevelArgs a{};
-    a.X = X; a.d = p.d; a.seed = p.seed; a.t = t;
+    a.X = X; a.d = p.d; a.seed = p.seed; a.n = p.n;
     a.perm_in = buf[l % 2]; a.perm_out = buf[(l + 1) % 2];
     a.ukeys = ukeys;
     a.segs = segs + lv.seg_begin;
@@ -220,41 +358,49 @@ int divide_core(const knng_params& p, int t, const Plan& pl, const void* plan_de
     a.pca_dirs = pca;
     HIP_TRY(launch_divide_level(a, s));
   }
-  if (leaf_off_dev)
-    HIP_TRY(hipMemcpyAsync(leaf_off_dev, (const char*)plan_dev + plan_leaf_off_offset(pl), pl.leaf_off.size() * 8,
-                           hipMemcpyDeviceToDevice, s));
   return KNNG_OK;
 }
 
-// Appends the plan's device image to `staging` (256-byte aligned blocks).
-void append_plan(const Plan& pl, std::vector<char>& staging) {
-  size_t a = pl.segs.size() * sizeof(SegDesc), b = pl.items.size() * sizeof(ItemDesc), c = pl.leaf_off.size() * 8;
-  size_t off = staging.size();
-  staging.resize(off + ((a + b + c + 255) & ~(size_t)255));
-  if (a) memcpy(staging.data() + off, pl.segs.data(), a);
-  if (b) memcpy(staging.data() + off + a, pl.items.data(), b);
-  if (c) memcpy(staging.data() + off + a + b, pl.leaf_off.data(), c);
+int upload_blob(const Batch& B, char* dst, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(dst, B.blob.data(), B.blob.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));   // the source may be dropped from the cache after this call
+  return KNNG_OK;
 }
 
-hipError_t zero_diag(void* diag, hipStream_t s) {
-  return launch_fill_u32((uint32_t*)diag, 0u, sizeof(DiagDev) / 4, s);
-}
-
-int leaf_core(const knng_params& p, const float* X, const uint32_t* perm, const int64_t* leaf_off, int64_t n_leaves,
-              uint32_t* ids, float* dist, char* ws, hipStream_t s) {
-  LeafLayout L = leaf_layout(p);
+int leaf_single(const knng_params& p, const float* X, const uint32_t* perm, const int64_t* leaf_off, int64_t n_leaves,
+                uint32_t* ids, float* dist, char* scratch, DiagDev* diag, hipStream_t s) {
+  LeafLayout L = leaf_layout(p, 1);
   LeafArgs a{};
   a.X = X; a.n = p.n; a.d = p.d; a.k = p.k; a.kp = p.k + p.rerank_m; a.precision = p.precision;
   a.perm = perm; a.leaf_off = leaf_off; a.n_leaves = n_leaves;
   a.ids = ids; a.dist = dist;
-  a.fallback = (uint32_t*)(ws + L.fallback);
-  a.diag = (DiagDev*)(ws + L.diag);
+  a.fallback = (uint32_t*)(scratch + L.fallback);
+  a.fallback_cap = (uint64_t)p.n;
+  a.diag = diag;
   HIP_TRY(launch_leaf(a, s));
   return KNNG_OK;
 }
 
-int prop_core(const knng_params& p, const float* X, uint32_t* ids, float* dist, int rounds, char* ws, hipStream_t s,
-              const std::function<hipError_t(int)>& after_round = nullptr) {
+int leaf_batched(const knng_params& p, const Batch& B, const char* blob_dev, const float* X, const uint32_t* perms,
+                 uint32_t* ids, float* dist, char* scratch, DiagDev* diag, hipStream_t s) {
+  LeafLayout L = leaf_layout(p, B.slots);
+  LeafArgs a{};
+  a.X = X; a.n = p.n; a.d = p.d; a.k = p.k; a.kp = p.k + p.rerank_m; a.precision = p.precision;
+  a.perm = perms;
+  a.ids = ids; a.dist = dist;
+  a.work = (const LeafWork*)(blob_dev + B.off_work);
+  a.n_work = (uint32_t)B.work.size();
+  a.counter = (uint32_t*)(scratch + L.counter);
+  a.grid = (uint32_t)cu_count();
+  a.fallback = (uint32_t*)(scratch + L.fallback);
+  a.fallback_cap = (uint64_t)B.slots * p.n;
+  a.diag = diag;
+  HIP_TRY(launch_leaf(a, s));
+  return KNNG_OK;
+}
+
+int prop_core(const knng_params& p, const float* X, uint32_t* ids, float* dist, int rounds, char* ws, DiagDev* diag,
+              const uint32_t* order, hipStream_t s, const std::function<hipError_t(int)>& after_round = nullptr) {
   PropLayout L = prop_layout(p);
   size_t nk = (size_t)p.n * p.k;
   uint32_t* tids = (uint32_t*)(ws + L.tmp_ids);
@@ -275,7 +421,8 @@ int prop_core(const knng_params& p, const float* X, uint32_t* ids, float* dist, 
     a.offs = (uint32_t*)(ws + L.offs);
     a.block_sums = (uint32_t*)(ws + L.bsum);
     a.bucket = (uint32_t*)(ws + L.bucket);
-    a.diag = (DiagDev*)(ws + L.diag);
+    a.order = order;
+    a.diag = diag;
     HIP_TRY(launch_propagate_round(a, s));
     if (after_round && !(r == rounds - 1 && rounds % 2 == 1)) HIP_TRY(after_round(r));
   }
@@ -405,11 +552,15 @@ size_t knng_workspace_bytes(const knng_params* p, int op) {
   if (validate(p) != KNNG_OK) return 0;
   switch (op) {
     case KNNG_OP_DIVIDE: {
-      DivideLayout L;
-      if (divide_layout(*p, 0, p->T, L) != KNNG_OK) return 0;
-      return L.total;
+      size_t mx = 0;
+      for (int t = 0; t < p->T; ++t) {
+        DivideLayout L;
+        if (divide_layout(*p, t, L) != KNNG_OK) return 0;
+        mx = std::max(mx, L.total);
+      }
+      return mx;
     }
-    case KNNG_OP_LEAF: return leaf_layout(*p).total;
+    case KNNG_OP_LEAF: return leaf_layout(*p, 1).total;
     case KNNG_OP_MERGE: return 0;
     case KNNG_OP_PROPAGATE: return prop_layout(*p).total;
     case KNNG_OP_BUILD: {
@@ -449,19 +600,24 @@ int knng_divide(const knng_params* p, int t, const float* X, const float* dir_ov
   if (!aligned16(X)) return fail(KNNG_EINVAL, "X must be 16-byte aligned");
   if (((uintptr_t)ws & 255) != 0) return fail(KNNG_EINVAL, "ws must be 256-byte aligned");
   DivideLayout L;
-  st = divide_layout(*p, t, t + 1, L);
+  st = divide_layout(*p, t, L);
   if (st) return st;
   if (ws_bytes < L.total) return fail(KNNG_ENOMEM, "divide needs %zu workspace bytes, got %zu", L.total, ws_bytes);
-  PlanPtr pl = get_plan(*p, t, &st);
-  if (!pl) return st;
+  BatchPtr B = get_batch(*p, {t}, &st);
+  if (!B) return st;
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
-  std::vector<char> staging;
-  append_plan(*pl, staging);
-  HIP_TRY(hipMemcpyAsync(w + L.plan, staging.data(), staging.size(), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));   // the staging buffer dies with this call
+  st = upload_blob(*B, w + L.blob, s);
+  if (st) return st;
   HIP_TRY(zero_diag(w + L.diag, s));
-  return divide_core(*p, t, *pl, w + L.plan, X, dir_override, dirs_out, perm, leaf_off, w, L, s);
+  uint32_t* tmp = (uint32_t*)(w + L.tmp);
+  uint32_t* b0 = (B->depth % 2 == 0) ? perm : tmp;   // the final permutation lands in `perm`
+  uint32_t* b1 = (B->depth % 2 == 0) ? tmp : perm;
+  st = divide_core(*p, *B, w + L.blob, X, dir_override, dirs_out, b0, b1, w + L.scratch, s);
+  if (st) return st;
+  if (leaf_off)
+    HIP_TRY(hipMemcpyAsync(leaf_off, w + L.blob + B->off_leaf, B->leaf_off0.size() * 8, hipMemcpyDeviceToDevice, s));
+  return KNNG_OK;
 }
 
 int knng_leaf_knn(const knng_params* p, const float* X, const uint32_t* perm, const int64_t* leaf_off,
@@ -471,18 +627,18 @@ int knng_leaf_knn(const knng_params* p, const float* X, const uint32_t* perm, co
   if (!X || !perm || !leaf_off || !ids || !dist || !ws) return fail(KNNG_EINVAL, "null array argument");
   if (!aligned16(X)) return fail(KNNG_EINVAL, "X must be 16-byte aligned");
   if (n_leaves < 1 || n_leaves > p->n) return fail(KNNG_EINVAL, "n_leaves=%lld out of [1, n]", (long long)n_leaves);
-  LeafLayout L = leaf_layout(*p);
+  LeafLayout L = leaf_layout(*p, 1);
   if (ws_bytes < L.total) return fail(KNNG_ENOMEM, "leaf_knn needs %zu workspace bytes, got %zu", L.total, ws_bytes);
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(zero_diag((char*)ws + L.diag, s));
-  return leaf_core(*p, X, perm, leaf_off, n_leaves, ids, dist, (char*)ws, s);
+  return leaf_single(*p, X, perm, leaf_off, n_leaves, ids, dist, (char*)ws, (DiagDev*)((char*)ws + L.diag), s);
 }
 
 int knng_merge(const knng_params* p, int n_lists, const uint32_t* ids_in, const float* dist_in, uint32_t* ids_out,
                float* dist_out, void* stream) {
   int st = validate(p);
   if (st) return st;
-  if (n_lists < 1 || n_lists > 1024) return fail(KNNG_EINVAL, "n_lists=%d out of [1, 4096]", n_lists);
+  if (n_lists < 1 || n_lists > 1024) return fail(KNNG_EINVAL, "n_lists=%d out of [1, 1024]", n_lists);
   if (!ids_in || !dist_in || !ids_out || !dist_out) return fail(KNNG_EINVAL, "null array argument");
   if ((int64_t)n_lists * p->k > 1024) return fail(KNNG_EUNSUPPORTED, "n_lists * k = %d exceeds 1024", n_lists * p->k);
   HIP_TRY(launch_merge(p->n, p->k, n_lists, ids_in, dist_in, ids_out, dist_out, (hipStream_t)stream));
@@ -501,9 +657,14 @@ int knng_propagate(const knng_params* p, const float* X, uint32_t* ids, float* d
   if (ws_bytes < L.total) return fail(KNNG_ENOMEM, "propagate needs %zu workspace bytes, got %zu", L.total, ws_bytes);
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(zero_diag((char*)ws + L.diag, s));
-  return prop_core(*p, X, ids, dist, rounds, (char*)ws, s);
+  return prop_core(*p, X, ids, dist, rounds, (char*)ws, (DiagDev*)((char*)ws + L.diag), nullptr, s);
 }
 
+// The whole method.  All T divisions advance level by level in batched
+// launches; one persistent launch then computes every leaf of every
+// division; the T lists are merged; the rounds run with points visited in
+// division 0's leaf order (neighbouring points share candidates, so their
+// rows stay in cache).
 static int build_impl(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
                       void* stream, std::vector<hipEvent_t>* ev) {
   int st = validate(p);
@@ -513,49 +674,36 @@ static int build_impl(const knng_params* p, const float* X, uint32_t* ids, float
   if (((uintptr_t)ws & 255) != 0) return fail(KNNG_EINVAL, "ws must be 256-byte aligned");
   if ((int64_t)p->T * p->k > 1024) return fail(KNNG_EUNSUPPORTED, "T * k = %d exceeds 1024", p->T * p->k);
   if (p->rounds > 0 && p->k > 31) return fail(KNNG_EUNSUPPORTED, "propagation supports k <= 31 (got %d)", p->k);
-  BuildLayout B;
-  st = build_layout(*p, B);
+  BuildLayout BL;
+  st = build_layout(*p, BL);
   if (st) return st;
-  if (ws_bytes < B.total) return fail(KNNG_ENOMEM, "build needs %zu workspace bytes, got %zu", B.total, ws_bytes);
+  if (ws_bytes < BL.total) return fail(KNNG_ENOMEM, "build needs %zu workspace bytes, got %zu", BL.total, ws_bytes);
+  BatchPtr B = get_batch(*p, all_divisions(*p), &st);
+  if (!B) return st;
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
-  // Every division's plan goes up in one copy before any kernel is queued.
-  std::vector<char> staging;
-  std::vector<PlanPtr> plans(p->T);
-  std::vector<size_t> plan_off(p->T);
-  for (int t = 0; t < p->T; ++t) {
-    plans[t] = get_plan(*p, t, &st);
-    if (!plans[t]) return st;
-    plan_off[t] = staging.size();
-    append_plan(*plans[t], staging);
-  }
-  HIP_TRY(hipMemcpyAsync(w + B.plans, staging.data(), staging.size(), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  char* sub = w + B.sub;
-  DivideLayout D;
-  st = divide_layout(*p, 0, p->T, D);
+  st = upload_blob(*B, w + BL.blob, s);
   if (st) return st;
-  size_t nk = (size_t)p->n * p->k;
-  uint32_t* lists_ids = (uint32_t*)(w + B.lists_ids);
-  float* lists_dist = (float*)(w + B.lists_dist);
-  uint32_t* perm = (uint32_t*)(w + B.perm);
-  int64_t* leaf_off = (int64_t*)(w + B.leaf_off);
-  // every sub-stage keeps its diagnostics at the start of the shared region
-  HIP_TRY(zero_diag(sub, s));
+  DiagDev* diag = (DiagDev*)(w + BL.diag);
+  HIP_TRY(zero_diag(diag, s));
   auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord((*ev)[i], s) : hipSuccess; };
+  uint32_t* permA = (uint32_t*)(w + BL.permA);
+  uint32_t* permB = (uint32_t*)(w + BL.permB);
+  uint32_t* lists_ids = (uint32_t*)(w + BL.lists_ids);
+  float* lists_dist = (float*)(w + BL.lists_dist);
+  char* sh = w + BL.shared;
   HIP_TRY(mark(0));
-  for (int t = 0; t < p->T; ++t) {
-    st = divide_core(*p, t, *plans[t], w + B.plans + plan_off[t], X, nullptr, nullptr, perm, leaf_off, sub, D, s);
-    if (st) return st;
-    HIP_TRY(mark(1 + 2 * t));
-    st = leaf_core(*p, X, perm, leaf_off, plans[t]->n_leaves(), lists_ids + t * nk, lists_dist + t * nk, sub, s);
-    if (st) return st;
-    HIP_TRY(mark(2 + 2 * t));
-  }
+  st = divide_core(*p, *B, w + BL.blob, X, nullptr, nullptr, permA, permB, sh, s);
+  if (st) return st;
+  const uint32_t* perms = (B->depth % 2 == 0) ? permA : permB;
+  HIP_TRY(mark(1));
+  st = leaf_batched(*p, *B, w + BL.blob, X, perms, lists_ids, lists_dist, sh, diag, s);
+  if (st) return st;
+  HIP_TRY(mark(2));
   HIP_TRY(launch_merge(p->n, p->k, p->T, lists_ids, lists_dist, ids, dist, s));
-  HIP_TRY(mark(1 + 2 * p->T));
+  HIP_TRY(mark(3));
   if (p->rounds > 0) {
-    st = prop_core(*p, X, ids, dist, p->rounds, sub, s, [&](int r) { return mark(2 + 2 * p->T + r); });
+    st = prop_core(*p, X, ids, dist, p->rounds, sh, diag, perms, s, [&](int r) { return mark(4 + r); });
     if (st) return st;
   }
   return KNNG_OK;
@@ -570,7 +718,7 @@ int knng_build_timed(const knng_params* p, const float* X, uint32_t* ids, float*
                      void* stream, float* ms_out, int ms_cap) {
   int st = validate(p);
   if (st) return st;
-  int nst = 2 * p->T + 1 + p->rounds;
+  int nst = 3 + p->rounds;
   if (!ms_out || ms_cap < nst) return fail(KNNG_EINVAL, "ms_out needs %d entries (got %d)", nst, ms_cap);
   std::vector<hipEvent_t> ev(nst + 1, nullptr);
   for (auto& e : ev)
@@ -592,15 +740,8 @@ int knng_read_diag(const knng_params* p, const void* ws, int op, knng_diag* out,
   int st = validate(p);
   if (st) return st;
   if (!ws || !out) return fail(KNNG_EINVAL, "null argument");
-  size_t off = 0;
-  if (op == KNNG_OP_BUILD) {
-    BuildLayout B;
-    st = build_layout(*p, B);
-    if (st) return st;
-    off = B.sub;   // the sub-stages share the diagnostics at the start of the shared region
-  }
-  DiagDev d{};
-  HIP_TRY(hipMemcpyAsync(&d, (const char*)ws + off, sizeof(d), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  DiagDev d{};   // every workspace layout starts with its diagnostics block
+  HIP_TRY(hipMemcpyAsync(&d, ws, sizeof(d), hipMemcpyDeviceToHost, (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   out->leaf_rows_fallback = (int64_t)d.leaf_fallback;
   out->leaf_rows = (int64_t)d.leaf_rows;

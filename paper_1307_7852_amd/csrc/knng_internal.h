@@ -43,14 +43,21 @@ struct SegDesc {          // one internal node of one level
   uint32_t off, m, left, v;
   uint32_t first_item;    // index of the node's first split item in the level's item list
   uint32_t n_items;
-  uint32_t dir_index;     // index of the node among all internal nodes (level order)
-  uint32_t pad;
+  uint32_t dir_index;     // index of the node's direction row (level order, batch-wide)
+  uint32_t t;             // division (keys the random draws)
+  uint32_t slot;          // batch slot: the division's permutation starts at slot * n
+  uint32_t pad[3];
 };
 struct ItemDesc {         // a chunk of positions handled by one workgroup
   uint32_t seg;           // level-local segment index (split items) or 0xFFFFFFFF (copy)
-  uint32_t start;         // first position
+  uint32_t start;         // first position (within the division)
   uint32_t len;
-  uint32_t pad;
+  uint32_t slot;          // batch slot of the division
+};
+struct LeafWork {         // one leaf of one division (batched leaf launch)
+  uint32_t slot;          // batch slot: permutation at slot * n, lists at slot * n * k
+  uint32_t m;             // leaf size
+  uint64_t off;           // leaf offset within the division's permutation
 };
 struct LevelPlan {
   uint32_t seg_begin, n_segs;      // into Plan::segs
@@ -102,12 +109,12 @@ struct DiagDev {
 // ------------------------------------------------------------------ launchers
 // Each returns hipSuccess or the first HIP error; they only enqueue.
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
-hipError_t launch_iota(uint32_t* p, uint32_t n, hipStream_t s);
+hipError_t launch_iota(uint32_t* p, uint32_t n, uint32_t slots, hipStream_t s);
 
 struct DivideLevelArgs {
-  const float* X; int d; uint64_t seed; int t;
-  const uint32_t* perm_in; uint32_t* perm_out;
-  uint32_t* ukeys;
+  const float* X; int d; uint64_t seed; int64_t n;
+  const uint32_t* perm_in; uint32_t* perm_out;   // slot-major: slot * n + position
+  uint32_t* ukeys;                                  // slot-major
   const SegDesc* segs;       // level's segments (device)
   const ItemDesc* items;     // level's items (device)
   uint32_t n_segs, n_split, n_items;
@@ -122,9 +129,14 @@ hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s);
 
 struct LeafArgs {
   const float* X; int64_t n; int d; int k; int kp; int precision;
-  const uint32_t* perm; const int64_t* leaf_off; int64_t n_leaves;
+  const uint32_t* perm; const int64_t* leaf_off; int64_t n_leaves;   // single-division mode
   uint32_t* ids; float* dist;
-  uint32_t* fallback;        // list of (leaf, position) pairs, capacity n
+  const LeafWork* work;      // batched mode (non-null): persistent workgroups pull leaves
+  uint32_t n_work;
+  uint32_t* counter;         // batched mode: next work item (zeroed by the launcher)
+  uint32_t grid;             // batched mode: workgroups launched
+  uint32_t* fallback;        // (leaf or work index, position) pairs, capacity fallback_cap
+  uint64_t fallback_cap;
   DiagDev* diag;
 };
 hipError_t launch_leaf(const LeafArgs& a, hipStream_t s);
@@ -143,6 +155,7 @@ struct PropArgs {
   uint32_t* offs;                         // n + 1
   uint32_t* block_sums;                   // scan scratch
   uint32_t* bucket;                       // (src, dist) pairs grouped by dst
+  const uint32_t* order;                  // nullable: the order points are processed in
   DiagDev* diag;
 };
 hipError_t launch_propagate_round(const PropArgs& a, hipStream_t s);

@@ -18,6 +18,7 @@
 // k_leaf_exact.
 #include "knng_dev.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace knng {
@@ -178,31 +179,29 @@ struct QFrag {
   }
 };
 
+// One leaf: members perm[off .. off+m), rows written to ids/dist (already
+// offset to the leaf's division).  `key` names the leaf in the fallback list.
 template <int KC, int KP, bool BF16>
-__global__ __launch_bounds__(LEAF_THREADS, 2) void k_leaf(LeafArgs a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  using Sh = LeafShared<KC, KP, BF16>;
+__device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, BF16>& S, const uint32_t* __restrict__ perm,
+                          uint32_t* __restrict__ ids_out, float* __restrict__ dist_out, int64_t off, int m, uint32_t key) {
   using Tile = TileT<KC, BF16>;
-  Sh& S = *reinterpret_cast<Sh*>(smem_raw);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, h = lane >> 5, r32 = lane & 31;
   const int d = a.d, k = a.k;
-  const int64_t L = blockIdx.x;
-  const int64_t off = a.leaf_off[L];
-  const int m = (int)(a.leaf_off[L + 1] - off);
+  const uint32_t L = key;
   if (m <= 0) return;
   if (tid == 0) atomicAdd(&a.diag->leaf_rows, (unsigned long long)m);
   if (m > KNNG_MAX_LEAF) {   // every row goes to the exact kernel
     for (int i = tid; i < m; i += LEAF_THREADS) {
       unsigned long long slot = atomicAdd(&a.diag->fallback_count, 1ull);
       atomicAdd(&a.diag->leaf_fallback, 1ull);
-      if (slot < (unsigned long long)a.n) {   // capacity n: leaves partition the points
-        a.fallback[2 * slot] = (uint32_t)L;
+      if (slot < a.fallback_cap) {   // capacity: every point of every division once
+        a.fallback[2 * slot] = L;
         a.fallback[2 * slot + 1] = (uint32_t)i;
       }
     }
     return;
   }
-  for (int i = tid; i < m; i += LEAF_THREADS) S.ids[i] = a.perm[off + i];
+  for (int i = tid; i < m; i += LEAF_THREADS) S.ids[i] = perm[off + i];
   if (tid == 0) S.flag = 1;
   __syncthreads();
   // ---- prologue: leaf mean (BF16), member norms, exactness flag, norm bounds
@@ -425,8 +424,8 @@ __global__ __launch_bounds__(LEAF_THREADS, 2) void k_leaf(LeafArgs a) {
       int qp = qbase + qj;
       if (qp < m && slot < k) {
         uint32_t qid = S.ids[qp];
-        a.ids[(size_t)qid * k + slot] = key_id(kv[r]);
-        a.dist[(size_t)qid * k + slot] = key_dist(kv[r]);
+        ids_out[(size_t)qid * k + slot] = key_id(kv[r]);
+        dist_out[(size_t)qid * k + slot] = key_dist(kv[r]);
         if (slot == k - 1) {
           // worst rejected candidate: the KP-th approximate value, if the list was full
           float vlast = vbuf[qj * KP + KP - 1];
@@ -453,8 +452,8 @@ __global__ __launch_bounds__(LEAF_THREADS, 2) void k_leaf(LeafArgs a) {
           if (!cert) {
             unsigned long long sl = atomicAdd(&a.diag->fallback_count, 1ull);
             atomicAdd(&a.diag->leaf_fallback, 1ull);
-            if (sl < (unsigned long long)a.n) {
-              a.fallback[2 * sl] = (uint32_t)L;
+            if (sl < a.fallback_cap) {
+              a.fallback[2 * sl] = L;
               a.fallback[2 * sl + 1] = (uint32_t)qp;
             }
           }
@@ -462,6 +461,49 @@ __global__ __launch_bounds__(LEAF_THREADS, 2) void k_leaf(LeafArgs a) {
       }
     }
     wave_sync();
+  }
+}
+
+// Single-division mode: one workgroup per leaf.  Batched mode: a persistent
+// grid; each workgroup takes the next leaf from the work list (largest
+// first) until the list is exhausted, so every workgroup reaches the exit.
+template <int KC, int KP, bool BF16>
+__global__ __launch_bounds__(LEAF_THREADS, 2) void k_leaf(LeafArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  using Sh = LeafShared<KC, KP, BF16>;
+  Sh& S = *reinterpret_cast<Sh*>(smem_raw);
+  __shared__ uint32_t next;
+  // single-division mode runs one pass of the loop for leaf blockIdx.x
+  for (uint32_t pass = 0;; ++pass) {
+    uint32_t idx;
+    if (a.work) {
+      if (threadIdx.x == 0) next = atomicAdd(a.counter, 1u);
+      __syncthreads();
+      idx = next;
+      __syncthreads();
+      if (idx >= a.n_work) break;
+    } else {
+      if (pass > 0) break;
+      idx = blockIdx.x;
+    }
+    const uint32_t* perm = a.perm;
+    uint32_t* ids_out = a.ids;
+    float* dist_out = a.dist;
+    int64_t off;
+    int m;
+    if (a.work) {
+      const LeafWork wk = a.work[idx];
+      perm += (size_t)wk.slot * a.n;
+      ids_out += (size_t)wk.slot * a.n * a.k;
+      dist_out += (size_t)wk.slot * a.n * a.k;
+      off = (int64_t)wk.off;
+      m = (int)wk.m;
+    } else {
+      off = a.leaf_off[idx];
+      m = (int)(a.leaf_off[idx + 1] - off);
+    }
+    leaf_body<KC, KP, BF16>(a, S, perm, ids_out, dist_out, off, m, idx);
+    __syncthreads();
   }
 }
 
@@ -473,12 +515,25 @@ __global__ __launch_bounds__(256) void k_leaf_exact(LeafArgs a) {
   __shared__ uint64_t best[64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   unsigned long long cnt = a.diag->fallback_count;
-  if (cnt > (unsigned long long)a.n) cnt = (unsigned long long)a.n;
+  if (cnt > a.fallback_cap) cnt = a.fallback_cap;
   for (unsigned long long it = blockIdx.x; it < cnt; it += gridDim.x) {
     const uint32_t L = a.fallback[2 * it], qp = a.fallback[2 * it + 1];
-    const int64_t off = a.leaf_off[L];
-    const int64_t m = a.leaf_off[L + 1] - off;
-    const uint32_t qid = a.perm[off + qp];
+    int64_t off, m;
+    const uint32_t* perm = a.perm;
+    uint32_t* ids_out = a.ids;
+    float* dist_out = a.dist;
+    if (a.work) {
+      const LeafWork wk = a.work[L];
+      off = (int64_t)wk.off;
+      m = wk.m;
+      perm += (size_t)wk.slot * a.n;
+      ids_out += (size_t)wk.slot * a.n * a.k;
+      dist_out += (size_t)wk.slot * a.n * a.k;
+    } else {
+      off = a.leaf_off[L];
+      m = a.leaf_off[L + 1] - off;
+    }
+    const uint32_t qid = perm[off + qp];
     const float* xq = a.X + (size_t)qid * a.d;
     if (tid < 64) best[tid] = ~0ull;
     __syncthreads();
@@ -489,7 +544,7 @@ __global__ __launch_bounds__(256) void k_leaf_exact(LeafArgs a) {
         int64_t cp = c0 + j;
         uint64_t key = ~0ull;
         if (cp < m) {   // uniform across the 16-lane group
-          uint32_t cid = a.perm[off + cp];
+          uint32_t cid = perm[off + cp];
           float dd = dist2_g16(xq, a.X + (size_t)cid * a.d, a.d, gl);
           if (cp != (int64_t)qp) key = pack_did(dd, cid);
         }
@@ -523,8 +578,8 @@ __global__ __launch_bounds__(256) void k_leaf_exact(LeafArgs a) {
       __syncthreads();
     }
     if (tid < a.k) {
-      a.ids[(size_t)qid * a.k + tid] = key_id(best[tid]);
-      a.dist[(size_t)qid * a.k + tid] = key_dist(best[tid]);
+      ids_out[(size_t)qid * a.k + tid] = key_id(best[tid]);
+      dist_out[(size_t)qid * a.k + tid] = key_dist(best[tid]);
     }
     __syncthreads();
   }
@@ -534,13 +589,23 @@ template <int KC, int KP, bool BF16>
 hipError_t launch_leaf_t(const LeafArgs& a, hipStream_t s) {
   size_t shm = sizeof(LeafShared<KC, KP, BF16>);
   auto kern = k_leaf<KC, KP, BF16>;
-  static bool attr_set = false;
-  if (!attr_set) {
+  static int per_cu = 0;
+  if (per_cu == 0) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
-    attr_set = true;
+    int occ = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, LEAF_THREADS, shm);
+    per_cu = (e == hipSuccess && occ > 0) ? occ : 1;
   }
-  hipLaunchKernelGGL(kern, dim3((unsigned)a.n_leaves), dim3(LEAF_THREADS), shm, s, a);
+  if (a.work) {
+    hipError_t e = launch_fill_u32(a.counter, 0u, 1, s);
+    if (e != hipSuccess) return e;
+    unsigned grid = (unsigned)std::min<uint64_t>(a.n_work, (uint64_t)a.grid * per_cu);
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(LEAF_THREADS), shm, s, a);
+  } else {
+    hipLaunchKernelGGL(kern, dim3((unsigned)a.n_leaves), dim3(LEAF_THREADS), shm, s, a);
+  }
   return hipGetLastError();
 }
 
