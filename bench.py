@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--rounds", type=int, default=None, help="override the propagation rounds")
     ap.add_argument("--queries", type=int, default=1000, help="recall sample size")
     ap.add_argument("--cpu-sample", type=int, default=20000, help="points for the CPU oracle leg (0: skip)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device (a plain copy kernel of known size, for scaling "
+                         "the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
@@ -136,6 +139,12 @@ def main():
                   precision=K.BF16 if w.precision == "bf16" else K.FP32, rerank_m=w.rerank_m, seed=w.seed + 1,
                   split=K.SPLIT_PCA if w.split == "pca" else K.SPLIT_RP, pca_iters=16)
     X_t = torch.from_numpy(X).to(dev)
+    if args.calibrate_copy:
+        src = torch.ones(2 ** 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ws = K.alloc_workspace(kp, K.OP_BUILD, dev)
     ids = torch.empty((w.n, w.k), dtype=torch.int32, device=dev)
     dist = torch.empty((w.n, w.k), dtype=torch.float32, device=dev)

@@ -12,7 +12,7 @@ import os
 from dataclasses import dataclass, fields
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libknng.so")
+LIB_PATH = os.environ.get("KNNG_LIB") or os.path.join(HERE, "libknng.so")
 
 NONE = 0xFFFFFFFF
 MAX_LEAF = 2048

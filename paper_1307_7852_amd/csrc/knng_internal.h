@@ -6,7 +6,7 @@
 #include <stddef.h>
 #include <vector>
 
-#include "../../include/knng.h"
+#include "knng.h"
 
 namespace knng {
 
