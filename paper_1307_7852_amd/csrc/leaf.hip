@@ -1,21 +1,27 @@
 // Exact k-NN inside every leaf subset (Section 3.1's brute-force subgraph).
 //
-// One workgroup (4 waves) per leaf.  The leaf's members stream through LDS in
-// tiles of 32 candidates x KC features (double-buffered, staged once for all
-// four waves, rows padded so the MFMA operand reads are bank-conflict free).
-// Each wave owns 32 queries (fragments in registers) and computes
-//   G[c][q] = x_c . x_q         (v_mfma_f32_32x32x2_f32, or the BF16 form
-//                                v_mfma_f32_32x32x16_bf16 on leaf-centred data)
-//   s[c][q] = |x_c|^2 - 2 G     (the query's own norm is constant per row)
-// A lane holds one query and 16 of every tile's 32 candidates; it keeps its
-// best KP candidates in a sorted register list fed through a small LDS
-// queue, so lanes with nothing to insert do not stall the others.  The two
-// lanes sharing a query exchange thresholds after every tile and merge their
-// lists in registers at the end.  The KP survivors are re-scored with the
-// canonical FP32 distance, sorted by (distance, id), and the first k written.
+// One workgroup (8 waves; 4 for k + rerank_m > 32) per leaf.  The leaf's
+// members stream through LDS in tiles of 32 candidates x KC features
+// (double-buffered, staged once for all waves; rows padded so operand reads
+// are bank-conflict free).  Each wave owns 32 queries whose fragments sit in
+// registers as the B operand, the tile supplies the A operand:
+//   G[c][q] = x_c . x_q   (v_mfma_f32_32x32x2_f32, or v_mfma_f32_32x32x16_bf16
+//                          on leaf-centred BF16 data)
+// so every lane holds 16 candidates of one query per tile.  Each becomes a
+// 32-bit key: the approximate squared distance |x_q|^2 + |x_c|^2 - 2 G as a
+// float with its 11 low mantissa bits replaced by the candidate's position
+// in the leaf.  Nonnegative normal floats order like their bit patterns, so
+// keeping a sorted top-KP list per lane costs one v_med3_f32 per list entry
+// and candidate.  The two lanes that share a query (each saw half of the
+// candidates) merge their lists; the KP survivors are re-scored with the
+// canonical FP32 distance, sorted by (distance, id) and the first k written.
 // A row whose k-th exact distance is not safely below every rejected
-// candidate's lower bound (from the Gram's error bound) is redone exactly by
-// k_leaf_exact.
+// candidate's lower bound (from the truncated key and the Gram's error bound)
+// is redone exactly by k_leaf_exact.
+//
+// Member norms, the exactness flag (all-integer data with small norms makes
+// the FP32 Gram exact) and the largest norm are gathered while the first
+// pass stages the tiles, so no separate sweep over the leaf is needed.
 #include "knng_dev.h"
 
 #include <algorithm>
@@ -28,69 +34,35 @@ namespace {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int LEAF_THREADS = 256;
 constexpr int QPW = 32;            // queries per wave
-constexpr int QPB = 128;           // queries per block pass
 constexpr int TILE = 32;           // candidates per tile
-constexpr int QUEUE = 8;           // per-lane queue slots (half a tile's share)
 constexpr int MU_MAX = 2048;       // BF16 path: d <= 2048
+constexpr uint32_t POS_MASK = 0x7FFu;          // position bits of a key (leaf <= 2048)
+constexpr uint32_t KEY_NONE = 0x7F7FFFFFu;     // FLT_MAX: above every key
+constexpr uint32_t KEY_VALID = 0x7F000000u;    // keys at or above this are padding
+constexpr float PAD_NORM = 3e38f;              // norm given to padding rows (keys land above KEY_VALID)
+constexpr float KEY_FLOOR = 0x1p-100f;         // keeps every key a normal float
 
 template <int KP>
-__device__ __forceinline__ void list_insert(float (&v)[KP], int (&p)[KP], float x, int px) {
-#pragma unroll
-  for (int s = KP - 1; s > 0; --s) {
-    bool sh = x < v[s - 1];
-    bool tk = x < v[s];
-    float nv = sh ? v[s - 1] : x;
-    int np = sh ? p[s - 1] : px;
-    v[s] = tk ? nv : v[s];
-    p[s] = tk ? np : p[s];
-  }
-  bool t0 = x < v[0];
-  v[0] = t0 ? x : v[0];
-  p[0] = t0 ? px : p[0];
-}
+struct Cfg {
+  static constexpr int WAVES = (KP <= 32) ? 8 : 4;
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int QPB = QPW * WAVES;   // queries per pass
+  static constexpr int LS = KP + 1;         // list stride per query in LDS
+};
 
-// (value, position) order with the empty entry (-1 as unsigned) last.
-__device__ __forceinline__ bool vp_less(float va, int pa, float vb, int pb) {
-  return va < vb || (va == vb && (unsigned)pa < (unsigned)pb);
+__device__ __forceinline__ float make_key(float dv, uint32_t pos) {
+  float v = fmaxf(dv, KEY_FLOOR);
+  return __uint_as_float((__float_as_uint(v) & ~POS_MASK) | pos);
 }
+__device__ __forceinline__ float key_value(uint32_t key) { return __uint_as_float(key & ~POS_MASK); }
 
-// Lanes l and l^32 hold sorted lists of the same query; both end with the
-// first KP of the union, sorted (a bitonic merge: the element-wise minimum of
-// one list and the other reversed holds the KP smallest, then half-cleaners).
+// Inserts x into the ascending list L (the largest entry falls off).
 template <int KP>
-__device__ __forceinline__ void pair_merge(float (&v)[KP], int (&p)[KP]) {
-  float ov[KP];
-  int op[KP];
+__device__ __forceinline__ void list_insert(float (&L)[KP], float x) {
 #pragma unroll
-  for (int s = 0; s < KP; ++s) {
-    ov[s] = __shfl_xor(v[s], 32);
-    op[s] = __shfl_xor(p[s], 32);
-  }
-#pragma unroll
-  for (int s = 0; s < KP; ++s) {
-    float bv = ov[KP - 1 - s];
-    int bp = op[KP - 1 - s];
-    bool tb = vp_less(bv, bp, v[s], p[s]);
-    v[s] = tb ? bv : v[s];
-    p[s] = tb ? bp : p[s];
-  }
-#pragma unroll
-  for (int stride = KP / 2; stride > 0; stride >>= 1) {
-#pragma unroll
-    for (int s = 0; s < KP; ++s) {
-      if ((s & stride) == 0) {
-        bool sw = vp_less(v[s + stride], p[s + stride], v[s], p[s]);
-        float tv = v[s];
-        int tp = p[s];
-        v[s] = sw ? v[s + stride] : v[s];
-        p[s] = sw ? p[s + stride] : p[s];
-        v[s + stride] = sw ? tv : v[s + stride];
-        p[s + stride] = sw ? tp : p[s + stride];
-      }
-    }
-  }
+  for (int j = KP - 1; j > 0; --j) L[j] = __builtin_amdgcn_fmed3f(L[j - 1], x, L[j]);
+  L[0] = fminf(L[0], x);
 }
 
 // Four canonical distances from one row to four rows (identical arithmetic
@@ -139,18 +111,19 @@ struct TileT {
 
 template <int KC, int KP, bool BF16>
 struct LeafShared {
+  using C = Cfg<KP>;
   uint32_t ids[KNNG_MAX_LEAF];
-  float nrm[KNNG_MAX_LEAF];
+  float nrm[KNNG_MAX_LEAF];                 // member norms (BF16: of the rounded centred rows)
   TileT<KC, BF16> tile[2];
   float mu[BF16 ? MU_MAX : 1];
-  float red[8];
-  int flag;
-  // per wave: the tile loop's queues (64 x QUEUE float2), then the re-rank
-  // buffers (positions, approximate values, exact distances: 3 x QPW x KP)
-  alignas(16) unsigned char scratch[4][(64 * QUEUE * 8 > 12 * QPW * KP) ? 64 * QUEUE * 8 : 12 * QPW * KP];
+  uint32_t max_n;                           // largest member norm (float bits)
+  int flag;                                 // FP32: every value integral and every norm <= 2^22
+  float qn[C::WAVES][QPW];                  // query norms, as used in the keys
+  uint32_t lst[C::WAVES][QPW * C::LS];      // merged top-KP keys per query
+  float dst[C::WAVES][QPW * C::LS];         // their canonical distances
 };
 
-// Query fragments in registers: lane (h, r) owns features [h*HALF, h*HALF+HALF)
+// Query fragments in registers: lane (h, q) owns features [h*HALF, h*HALF+HALF)
 // of each KC-wide chunk; MFMA step s uses feature h*HALF + s (FP32) or
 // h*HALF + 8 s .. +7 (BF16).  Tiles use the same mapping for the candidates,
 // so the contraction covers every feature exactly once.
@@ -183,15 +156,18 @@ struct QFrag {
 // offset to the leaf's division).  `key` names the leaf in the fallback list.
 template <int KC, int KP, bool BF16>
 __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, BF16>& S, const uint32_t* __restrict__ perm,
-                          uint32_t* __restrict__ ids_out, float* __restrict__ dist_out, int64_t off, int m, uint32_t key) {
+                                          uint32_t* __restrict__ ids_out, float* __restrict__ dist_out, int64_t off,
+                                          int m, uint32_t key) {
+  using C = Cfg<KP>;
   using Tile = TileT<KC, BF16>;
+  constexpr int LS = C::LS;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, h = lane >> 5, r32 = lane & 31;
   const int d = a.d, k = a.k;
   const uint32_t L = key;
   if (m <= 0) return;
   if (tid == 0) atomicAdd(&a.diag->leaf_rows, (unsigned long long)m);
   if (m > KNNG_MAX_LEAF) {   // every row goes to the exact kernel
-    for (int i = tid; i < m; i += LEAF_THREADS) {
+    for (int i = tid; i < m; i += C::THREADS) {
       unsigned long long slot = atomicAdd(&a.diag->fallback_count, 1ull);
       atomicAdd(&a.diag->leaf_fallback, 1ull);
       if (slot < a.fallback_cap) {   // capacity: every point of every division once
@@ -201,58 +177,39 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     }
     return;
   }
-  for (int i = tid; i < m; i += LEAF_THREADS) S.ids[i] = perm[off + i];
-  if (tid == 0) S.flag = 1;
+  for (int i = tid; i < m; i += C::THREADS) S.ids[i] = perm[off + i];
+  if (tid == 0) {
+    S.flag = 1;
+    S.max_n = 0u;
+  }
   __syncthreads();
-  // ---- prologue: leaf mean (BF16), member norms, exactness flag, norm bounds
+  // ---- BF16: leaf mean, coalesced (threads over features x row groups)
   if constexpr (BF16) {
-    for (int j = tid; j < d; j += LEAF_THREADS) {
+    float* part = reinterpret_cast<float*>(&S.tile[0]);   // >= THREADS floats, free until staging
+    const int dd = d < C::THREADS ? d : C::THREADS;
+    const int G = C::THREADS / dd;
+    for (int jb = 0; jb < d; jb += dd) {
+      const int jl = tid % dd, g = tid / dd, j = jb + jl;
       float acc = 0.f;
-      for (int i = 0; i < m; ++i) acc += a.X[(size_t)S.ids[i] * d + j];
-      S.mu[j] = acc / (float)m;
-    }
-    __syncthreads();
-  }
-  float my_max_n = 0.f, my_max_c = 0.f;
-  int all_int = 1;
-  for (int i = w; i < m; i += 4) {            // a wave per member row, lanes over features
-    const float* x = a.X + (size_t)S.ids[i] * d;
-    float nacc = 0.f, cacc = 0.f;
-    for (int j = lane; j < d; j += 64) {
-      float v = x[j];
-      if (BF16) {
-        float c = v - S.mu[j];
-        float t = bf16_round(c);
-        nacc = __builtin_fmaf(t, t, nacc);
-        cacc = __builtin_fmaf(c, c, cacc);
-      } else {
-        nacc = __builtin_fmaf(v, v, nacc);
-        all_int &= (v == rintf(v));
+      if (g < G && j < d)
+        for (int i = g; i < m; i += G) acc += a.X[(size_t)S.ids[i] * d + j];
+      if (g < G) part[g * dd + jl] = acc;
+      __syncthreads();
+      if (tid < dd && jb + tid < d) {
+        float s = 0.f;
+        for (int gg = 0; gg < G; ++gg) s += part[gg * dd + tid];
+        S.mu[jb + tid] = s / (float)m;
       }
+      __syncthreads();
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      nacc += __shfl_xor(nacc, o);
-      cacc += __shfl_xor(cacc, o);
-    }
-    if (!BF16) all_int &= (nacc <= 4194304.0f);   // 2^22: every Gram partial sum exact
-    if (lane == 0) S.nrm[i] = nacc;
-    my_max_n = fmaxf(my_max_n, nacc);
-    my_max_c = fmaxf(my_max_c, cacc);
   }
-  if (lane == 0) { S.red[w] = my_max_n; S.red[4 + w] = my_max_c; }
-  if (!all_int) S.flag = 0;
-  __syncthreads();
-  const float max_n = fmaxf(fmaxf(S.red[0], S.red[1]), fmaxf(S.red[2], S.red[3]));
-  const float max_c = sqrtf(fmaxf(fmaxf(S.red[4], S.red[5]), fmaxf(S.red[6], S.red[7])));
-  const bool exact_gram = !BF16 && S.flag;
   const float eps_c = 2.0f * (float)(d + 4) * 5.9604645e-8f;   // 2 (d+4) 2^-24
+  const float INF = __int_as_float(0x7F800000);
 
-  unsigned char* scr = S.scratch[w];
-  float2* myq = reinterpret_cast<float2*>(scr) + lane * QUEUE;
   constexpr int HALF = KC / 2;
   constexpr int F4_PER_ROW = KC / 4;
-  constexpr int STAGE_F4 = TILE * F4_PER_ROW / LEAF_THREADS;   // float4 per thread per tile chunk
-  static_assert(STAGE_F4 >= 1, "tile too small for the block");
+  constexpr int TILE_F4 = TILE * F4_PER_ROW;
+  constexpr int STAGE_F4 = (TILE_F4 + C::THREADS - 1) / C::THREADS;   // float4 per thread per tile chunk
   const int nchunk = (d + KC - 1) / KC;
   const int ntile = (m + TILE - 1) / TILE;
   const int nsteps = ntile * nchunk;
@@ -262,52 +219,117 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     int c0 = (st / nchunk) * TILE, kc = (st % nchunk) * KC;
 #pragma unroll
     for (int u = 0; u < STAGE_F4; ++u) {
-      int e = tid + u * LEAF_THREADS;
-      int row = e / F4_PER_ROW, col = (e % F4_PER_ROW) * 4;
-      int cp = c0 + row;
+      int e = tid + u * C::THREADS;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (cp < m && kc + col < d) v = *(const float4*)(a.X + (size_t)S.ids[cp] * d + kc + col);
+      if (e < TILE_F4) {
+        int row = e / F4_PER_ROW, col = (e % F4_PER_ROW) * 4;
+        int cp = c0 + row;
+        if (cp < m && kc + col < d) v = *(const float4*)(a.X + (size_t)S.ids[cp] * d + kc + col);
+      }
       rg[u] = v;
     }
   };
-  auto stage_store = [&](int st, int buf, const float4 (&rg)[STAGE_F4]) {
-    int kc = (st % nchunk) * KC;
+  // registers -> LDS; on the first pass also the member norms (rows of a
+  // tile are held by F4_PER_ROW consecutive lanes, reduced by shuffles)
+  auto stage_store = [&](int st, int buf, const float4 (&rg)[STAGE_F4], bool norms) {
+    int c0 = (st / nchunk) * TILE, kci = st % nchunk, kc = kci * KC;
 #pragma unroll
     for (int u = 0; u < STAGE_F4; ++u) {
-      int e = tid + u * LEAF_THREADS;
+      int e = tid + u * C::THREADS;
       int row = e / F4_PER_ROW, col = (e % F4_PER_ROW) * 4;
+      float4 v = rg[u];
+      float sq;
       if constexpr (!BF16) {
-        *(float4*)&S.tile[buf].v[row * Tile::STRIDE + col] = rg[u];
+        if (e < TILE_F4) *(float4*)&S.tile[buf].v[row * Tile::STRIDE + col] = v;
+        sq = __builtin_fmaf(v.x, v.x, __builtin_fmaf(v.y, v.y, __builtin_fmaf(v.z, v.z, v.w * v.w)));
+        if (norms && (v.x != rintf(v.x) || v.y != rintf(v.y) || v.z != rintf(v.z) || v.w != rintf(v.w))) S.flag = 0;
       } else {
-        float4 v = rg[u];
-        bool in = kc + col < d;   // padded features stay exactly zero
-        __bf16* dst = &S.tile[buf].v[row * Tile::STRIDE + col];
-        dst[0] = (__bf16)(in ? v.x - S.mu[kc + col] : 0.f);
-        dst[1] = (__bf16)(in ? v.y - S.mu[kc + col + 1] : 0.f);
-        dst[2] = (__bf16)(in ? v.z - S.mu[kc + col + 2] : 0.f);
-        dst[3] = (__bf16)(in ? v.w - S.mu[kc + col + 3] : 0.f);
+        bool in = e < TILE_F4 && kc + col < d;   // padded features stay exactly zero
+        float t0 = in ? bf16_round(v.x - S.mu[kc + col]) : 0.f;
+        float t1 = in ? bf16_round(v.y - S.mu[kc + col + 1]) : 0.f;
+        float t2 = in ? bf16_round(v.z - S.mu[kc + col + 2]) : 0.f;
+        float t3 = in ? bf16_round(v.w - S.mu[kc + col + 3]) : 0.f;
+        if (e < TILE_F4) {
+          __bf16* dst = &S.tile[buf].v[row * Tile::STRIDE + col];
+          dst[0] = (__bf16)t0;
+          dst[1] = (__bf16)t1;
+          dst[2] = (__bf16)t2;
+          dst[3] = (__bf16)t3;
+        }
+        sq = __builtin_fmaf(t0, t0, __builtin_fmaf(t1, t1, __builtin_fmaf(t2, t2, t3 * t3)));
+      }
+      if (norms) {   // uniform
+#pragma unroll
+        for (int o = F4_PER_ROW / 2; o > 0; o >>= 1) sq += __shfl_xor(sq, o, F4_PER_ROW);
+        if (e < TILE_F4 && (e % F4_PER_ROW) == 0) {
+          int cp = c0 + row;
+          float tot = (cp < m) ? ((kci == 0) ? sq : S.nrm[cp] + sq) : PAD_NORM;
+          S.nrm[cp] = tot;
+          if (kci == nchunk - 1 && cp < m) {
+            atomicMax(&S.max_n, __float_as_uint(tot));
+            if (!BF16 && tot > 4194304.0f) S.flag = 0;   // 2^22: partial Gram sums stay exact
+          }
+        }
       }
     }
   };
 
-  for (int qb = 0; qb < m; qb += QPB) {
+  for (int qb = 0; qb < m; qb += C::QPB) {
+    const bool first = qb == 0;
     const int qbase = qb + w * QPW;
     const bool wave_on = qbase < m;           // uniform per wave
-    const int qpos = qbase + r32;
+    const int qpos = qbase + r32;             // this lane's query
     const bool qok = qpos < m;
     const float* qrow = a.X + (size_t)S.ids[qok ? qpos : 0] * d;
     QFrag<KC, BF16> qf;
-    if (nchunk == 1 && wave_on) qf.load(qrow, 0, d, h, S.mu, qok);
-    float lv[KP];
-    int lp[KP];
+    // query norm over the lane's half of every chunk, then across the pair
+    float nq = 0.f;
+    if (wave_on) {
+      if (nchunk == 1) {
+        qf.load(qrow, 0, d, h, S.mu, qok);
+        if constexpr (!BF16) {
 #pragma unroll
-    for (int s = 0; s < KP; ++s) { lv[s] = __int_as_float(0x7F800000); lp[s] = -1; }
-    float thr_pair = __int_as_float(0x7F800000);
+          for (int i = 0; i < QFrag<KC, BF16>::N4; ++i) {
+            nq = __builtin_fmaf(qf.f[i].x, qf.f[i].x, nq);
+            nq = __builtin_fmaf(qf.f[i].y, qf.f[i].y, nq);
+            nq = __builtin_fmaf(qf.f[i].z, qf.f[i].z, nq);
+            nq = __builtin_fmaf(qf.f[i].w, qf.f[i].w, nq);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < QFrag<KC, BF16>::N8; ++i)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) nq = __builtin_fmaf((float)qf.b[i][e], (float)qf.b[i][e], nq);
+        }
+      } else {
+        for (int kc = 0; kc < d; kc += KC) {
+#pragma unroll 4
+          for (int c = kc + h * HALF; c < kc + h * HALF + HALF; c += 4) {
+            float4 v = (qok && c < d) ? *(const float4*)(qrow + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (BF16 && qok && c < d) {
+              v.x = bf16_round(v.x - S.mu[c]);
+              v.y = bf16_round(v.y - S.mu[c + 1]);
+              v.z = bf16_round(v.z - S.mu[c + 2]);
+              v.w = bf16_round(v.w - S.mu[c + 3]);
+            }
+            nq = __builtin_fmaf(v.x, v.x, nq);
+            nq = __builtin_fmaf(v.y, v.y, nq);
+            nq = __builtin_fmaf(v.z, v.z, nq);
+            nq = __builtin_fmaf(v.w, v.w, nq);
+          }
+        }
+      }
+      nq += __shfl_xor(nq, 32);
+      if (h == 0) S.qn[w][r32] = nq;
+    }
+    float Lk[KP];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) Lk[j] = __uint_as_float(KEY_NONE);
     f32x16 acc0 = {0}, acc1 = {0};
     {
       float4 rg[STAGE_F4];
       stage_load(0, rg);
-      stage_store(0, 0, rg);
+      stage_store(0, 0, rg, first);
     }
     __syncthreads();
     for (int st = 0; st < nsteps; ++st) {
@@ -326,60 +348,65 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
           const float4* trow = reinterpret_cast<const float4*>(&S.tile[buf].v[r32 * Tile::STRIDE + h * HALF]);
 #pragma unroll
           for (int i = 0; i < HALF / 4; ++i) {
-            float4 av = trow[i];
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, qf.f[i].x, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, qf.f[i].y, acc1, 0, 0, 0);
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, qf.f[i].z, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, qf.f[i].w, acc1, 0, 0, 0);
+            float4 cv = trow[i];
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.x, qf.f[i].x, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.y, qf.f[i].y, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.z, qf.f[i].z, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.w, qf.f[i].w, acc1, 0, 0, 0);
           }
         } else {
           const bf16x8* trow = reinterpret_cast<const bf16x8*>(&S.tile[buf].v[r32 * Tile::STRIDE + h * HALF]);
 #pragma unroll
           for (int i = 0; i < HALF / 8; ++i) {
-            bf16x8 av = trow[i];
-            if (i % 2 == 0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, qf.b[i], acc0, 0, 0, 0);
-            else acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, qf.b[i], acc1, 0, 0, 0);
+            bf16x8 cv = trow[i];
+            if (i % 2 == 0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cv, qf.b[i], acc0, 0, 0, 0);
+            else acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cv, qf.b[i], acc1, 0, 0, 0);
           }
         }
         if (kci == nchunk - 1) {
-          // filter this tile into the lane's queue, half a tile at a time
+          // register r holds candidate c0 + 8(r/4) + 4h + r%4 against this lane's query
+          float4 n4[4];
 #pragma unroll
-          for (int half = 0; half < 2; ++half) {
-            int cnt = 0;
+          for (int g = 0; g < 4; ++g) n4[g] = *reinterpret_cast<const float4*>(&S.nrm[c0 + 8 * g + 4 * h]);
+          const uint32_t pbase = (uint32_t)(c0 + 4 * h);
+          const bool diag = (c0 == qbase);   // uniform: the tile holding the wave's own queries
 #pragma unroll
-            for (int rr = 0; rr < 8; ++rr) {
-              const int r = half * 8 + rr;
-              int ci = 8 * (r >> 2) + 4 * h + (r & 3);
-              int cp = c0 + ci;
-              float g = acc0[r] + acc1[r];
-              float sv = (cp < m ? S.nrm[cp] : 0.f) - 2.0f * g;
-              bool ok = qok && cp < m && cp != qpos && (sv < lv[KP - 1]) && (sv <= thr_pair);
-              if (ok) myq[cnt] = make_float2(sv, __int_as_float(cp));
-              cnt += ok ? 1 : 0;
-            }
-            for (int q = 0; __any(q < cnt); ++q) {
-              if (q < cnt) {
-                float2 e = myq[q];
-                if (e.x < lv[KP - 1]) list_insert<KP>(lv, lp, e.x, __float_as_int(e.y));
-              }
-            }
+          for (int r = 0; r < 16; ++r) {
+            const int cl = 8 * (r >> 2) + (r & 3);
+            const float nc = (r & 3) == 0 ? n4[r >> 2].x : (r & 3) == 1 ? n4[r >> 2].y : (r & 3) == 2 ? n4[r >> 2].z : n4[r >> 2].w;
+            const float dv = __builtin_fmaf(-2.0f, acc0[r] + acc1[r], nq + nc);
+            float x = make_key(dv, pbase + (uint32_t)cl);
+            if (diag && (cl + 4 * h == r32)) x = __uint_as_float(KEY_NONE);
+            list_insert<KP>(Lk, x);
           }
-          thr_pair = __shfl_xor(lv[KP - 1], 32);
         }
       }
-      if (more) stage_store(st + 1, buf ^ 1, rg);
+      if (more) stage_store(st + 1, buf ^ 1, rg, first);
       __syncthreads();
     }
     if (!wave_on) continue;                   // no barrier below this point
-    // ---- merge the two half-lists of each query (both lanes end with it)
-    pair_merge<KP>(lv, lp);
-    int* pb = reinterpret_cast<int*>(scr);                       // [QPW][KP] candidate positions
-    float* vbuf = reinterpret_cast<float*>(scr) + QPW * KP;      // [QPW][KP] approximate values
-    float* dex = reinterpret_cast<float*>(scr) + 2 * QPW * KP;   // [QPW][KP] exact distances
-    wave_sync();
-    if (h == 0) {
+    // ---- merge the two half-lists of each query: the KP smallest of both
+    {
+      float P[KP];
 #pragma unroll
-      for (int s2 = 0; s2 < KP; ++s2) { pb[r32 * KP + s2] = lp[s2]; vbuf[r32 * KP + s2] = lv[s2]; }
+      for (int j = 0; j < KP; ++j) P[j] = __shfl_xor(Lk[j], 32);
+#pragma unroll
+      for (int j = 0; j < KP; ++j) Lk[j] = fminf(Lk[j], P[KP - 1 - j]);
+#pragma unroll
+      for (int s = KP / 2; s > 0; s >>= 1) {
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+          if ((j & s) == 0) {
+            float lo = fminf(Lk[j], Lk[j + s]), hi = fmaxf(Lk[j], Lk[j + s]);
+            Lk[j] = lo;
+            Lk[j + s] = hi;
+          }
+        }
+      }
+      if (h == 0) {
+#pragma unroll
+        for (int j = 0; j < KP; ++j) S.lst[w][r32 * LS + j] = __float_as_uint(Lk[j]);
+      }
     }
     wave_sync();
     // ---- exact re-rank: groups of 16 lanes, four pairs of one query at a time
@@ -391,17 +418,20 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
         const float* xq = a.X + (size_t)S.ids[qp < m ? qp : 0] * d;
         const float* xc[4];
         bool ok[4];
+        int ee[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          int cp = pb[blk + g + 4 * u];
-          ok[u] = cp >= 0 && qp < m;
-          xc[u] = a.X + (size_t)S.ids[ok[u] ? cp : 0] * d;
+          ee[u] = (blk % KP) + g + 4 * u;
+          uint32_t kk = S.lst[w][qj * LS + ee[u]];
+          ok[u] = kk < KEY_VALID && qp < m;
+          int cp = ok[u] ? (int)(kk & POS_MASK) : 0;
+          xc[u] = a.X + (size_t)S.ids[cp] * d;
         }
         float dd[4];
         dist2_g16_x4(xq, xc, d, gl, dd);
         if (gl == 0) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) dex[blk + g + 4 * u] = ok[u] ? dd[u] : __int_as_float(0x7F800000);
+          for (int u = 0; u < 4; ++u) S.dst[w][qj * LS + ee[u]] = ok[u] ? dd[u] : INF;
         }
       }
     }
@@ -412,10 +442,13 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       int e = r * 64 + lane;
-      int cp = pb[e];
-      kv[r] = cp >= 0 ? pack_did(dex[e], S.ids[cp]) : ~0ull;
+      int qj = e / KP, slot = e % KP;
+      uint32_t kk = S.lst[w][qj * LS + slot];
+      kv[r] = kk < KEY_VALID ? pack_did(S.dst[w][qj * LS + slot], S.ids[kk & POS_MASK]) : ~0ull;
     }
     wave_bitonic<R, KP, uint64_t>(kv, lane);
+    const float max_n = __uint_as_float(S.max_n);
+    const bool exact_gram = !BF16 && S.flag;
     // write rows, check the certificate on slot k-1
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -427,24 +460,23 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
         ids_out[(size_t)qid * k + slot] = key_id(kv[r]);
         dist_out[(size_t)qid * k + slot] = key_dist(kv[r]);
         if (slot == k - 1) {
-          // worst rejected candidate: the KP-th approximate value, if the list was full
-          float vlast = vbuf[qj * KP + KP - 1];
-          bool full = pb[qj * KP + KP - 1] >= 0;
+          // every candidate outside the list has a key at least the KP-th's
+          uint32_t kl = S.lst[w][qj * LS + KP - 1];
           bool cert = true;
-          if (full && !exact_gram) {
-            float nq = S.nrm[qp];
-            float dt = nq + vlast;                         // approximate distance of the boundary
-            float e32 = eps_c * (nq + max_n);
+          if (kl < KEY_VALID) {
+            float vlast = key_value(kl) - 2.0f * KEY_FLOOR;
+            float nq = S.qn[w][qj];
             float lb;
-            if (BF16) {
-              float xq = 0.f;
-              const float* xr = a.X + (size_t)qid * d;
-              for (int j = 0; j < d; ++j) { float c = xr[j] - S.mu[j]; xq = __builtin_fmaf(c, c, xq); }
-              float delta = (0.00390625f + 1.2e-7f) * (sqrtf(xq) + max_c) * 1.001f;
-              float rt = sqrtf(fmaxf(dt - e32, 0.f)) - delta;
+            if (exact_gram) {
+              lb = vlast;
+            } else if (BF16) {
+              float e32 = eps_c * (nq + max_n);
+              // rounding each centred row to BF16 moves it by at most 2^-8 of its norm
+              float delta = (0.00390625f + 1.2e-7f) * 1.0025f * (sqrtf(nq) + sqrtf(max_n)) * 1.001f;
+              float rt = sqrtf(fmaxf(vlast - e32, 0.f)) - delta;
               lb = rt > 0.f ? rt * rt * 0.9999f : 0.f;
             } else {
-              lb = dt - e32;
+              lb = vlast - eps_c * (nq + max_n);
             }
             float dk = key_dist(kv[r]);
             cert = lb > dk * (1.0f + 2e-6f);
@@ -468,7 +500,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
 // grid; each workgroup takes the next leaf from the work list (largest
 // first) until the list is exhausted, so every workgroup reaches the exit.
 template <int KC, int KP, bool BF16>
-__global__ __launch_bounds__(LEAF_THREADS, 2) void k_leaf(LeafArgs a) {
+__global__ __launch_bounds__(Cfg<KP>::THREADS) void k_leaf(LeafArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using Sh = LeafShared<KC, KP, BF16>;
   Sh& S = *reinterpret_cast<Sh*>(smem_raw);
@@ -589,12 +621,13 @@ template <int KC, int KP, bool BF16>
 hipError_t launch_leaf_t(const LeafArgs& a, hipStream_t s) {
   size_t shm = sizeof(LeafShared<KC, KP, BF16>);
   auto kern = k_leaf<KC, KP, BF16>;
+  constexpr int THREADS = Cfg<KP>::THREADS;
   static int per_cu = 0;
   if (per_cu == 0) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     int occ = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, LEAF_THREADS, shm);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, THREADS, shm);
     per_cu = (e == hipSuccess && occ > 0) ? occ : 1;
   }
   if (a.work) {
@@ -602,9 +635,9 @@ hipError_t launch_leaf_t(const LeafArgs& a, hipStream_t s) {
     if (e != hipSuccess) return e;
     unsigned grid = (unsigned)std::min<uint64_t>(a.n_work, (uint64_t)a.grid * per_cu);
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(LEAF_THREADS), shm, s, a);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(THREADS), shm, s, a);
   } else {
-    hipLaunchKernelGGL(kern, dim3((unsigned)a.n_leaves), dim3(LEAF_THREADS), shm, s, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)a.n_leaves), dim3(THREADS), shm, s, a);
   }
   return hipGetLastError();
 }
