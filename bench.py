@@ -89,6 +89,46 @@ def read_traffic(kernel_src, name):
         return None
 
 
+def exact_ids(X, queries, k, block=4096):
+    """Exact k nearest ids (self excluded) of the query points, float64."""
+    Xd = X.astype(np.float64)
+    nrm = (Xd * Xd).sum(1)
+    out = np.empty((len(queries), k), dtype=np.int64)
+    for s in range(0, len(queries), 64):
+        q = queries[s:s + 64]
+        D = nrm[q][:, None] + nrm[None, :] - 2.0 * (Xd[q] @ Xd.T)
+        D[np.arange(len(q)), q] = np.inf
+        part = np.argpartition(D, k, axis=1)[:, :k]
+        dd = np.take_along_axis(D, part, 1)
+        out[s:s + 64] = np.take_along_axis(part, np.argsort(dd, 1, kind="stable"), 1)
+    return out
+
+
+def train_partitioner(K, torch, dev, steps, X1=None):
+    """The learned division's network, trained on the graph the plain method
+    builds for the 1M SIFT-like workload (training time is reported, not
+    counted in points/s)."""
+    w1 = datagen.WORKLOADS["sift1m"]
+    if X1 is None:
+        X1 = datagen.make(w1)
+    X1_t = torch.from_numpy(X1).to(dev)
+    kp1 = K.Params(n=w1.n, d=w1.d, k=w1.k, T=w1.T, leaf_max=w1.leaf_max, rounds=w1.rounds, pairwise=1,
+                   split=K.SPLIT_PCA, seed=w1.seed + 1)
+    ids1, _ = K.knn_graph(X1_t, kp1)
+    torch.cuda.synchronize()
+    part = K.Partitioner(w1.d, seed=w1.seed + 7)
+    t0 = time.perf_counter()
+    losses = part.train(X1_t, ids1, k=w1.k, steps=steps, seed=w1.seed + 9, n_pos=4096, n_neg=4096)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    l = losses.cpu().numpy()
+    del X1_t, ids1
+    torch.cuda.empty_cache()
+    return part, {"steps": steps, "pairs_per_step": 8192, "seconds": round(dt, 3),
+                  "loss_first": float(l[:10].mean()), "loss_last": float(l[-10:].mean()),
+                  "graph": "sift1m plain build (principal-direction divisions, T=8, 3 rounds)"}
+
+
 def cpu_baseline(w, n_sample):
     """The CPU oracle (float64, single-threaded NumPy) on a bounded sample of
     the same workload: n_sample points drawn from the same generator."""
@@ -97,7 +137,7 @@ def cpu_baseline(w, n_sample):
     op = O.Params(n=n_sample, d=w.d, k=w.k, T=w.T, leaf_max=w.leaf_max, leaf_cap_cycle=w.leaf_cap_cycle,
                   q_lo_pm=w.q_lo_pm, q_hi_pm=w.q_hi_pm, rounds=w.rounds, pairwise=True, seed=w.seed + 1)
     t0 = time.perf_counter()
-    O.build(Xs, op, split=w.split)
+    O.build(Xs, op, split="pca" if w.split == "pca" else "rp")
     dt = time.perf_counter() - t0
     return {"value": round(n_sample / dt, 2), "unit": "points/s", "cores": 1, "kind": "oracle",
             "sample": f"whole method on {n_sample} points of the same generator ({dt:.1f} s); "
@@ -114,6 +154,7 @@ def main():
     ap.add_argument("--rounds", type=int, default=None, help="override the propagation rounds")
     ap.add_argument("--queries", type=int, default=1000, help="recall sample size")
     ap.add_argument("--cpu-sample", type=int, default=20000, help="points for the CPU oracle leg (0: skip)")
+    ap.add_argument("--train-steps", type=int, default=1500, help="Adam steps for the learned division")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a plain copy kernel of known size, for scaling "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -145,12 +186,46 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    learned = w.split == "learned"
+    split_desc = ("principal direction (16 FP32 power iterations on 256 samples)" if w.split == "pca"
+                  else "random projection")
+    train_info = choice = None
+    if learned:
+        log(f"training the partitioner ({args.train_steps} steps)")
+        part, train_info = train_partitioner(K, torch, dev, args.train_steps, X if w.name.startswith("sift1m") else None)
+        log(f"  {train_info}")
+        Z = part.embed(X_t)
+        # fallback rule on held-out exact neighbour pairs (not the recall queries)
+        hq = datagen.query_sample(w.n, 300, w.seed + 77)
+        hp = np.stack([np.repeat(hq, w.k), exact_ids(X, hq, w.k).reshape(-1)], 1)
+        kpc = K.Params(n=w.n, d=w.d, k=w.k, T=1, leaf_max=w.leaf_max, seed=w.seed + 1)
+        use, r_plain, r_learned = K.learned_choice(kpc, X_t, Z, torch.from_numpy(hp.astype(np.int32)).to(dev),
+                                                   K.alloc_workspace(kpc, K.OP_COLEAF, dev))
+        choice = {"use_learned": use, "coleaf_plain_rp": round(r_plain, 4), "coleaf_learned": round(r_learned, 4),
+                  "held_out_pairs": int(len(hp))}
+        log(f"  fallback rule: {choice}")
+        split_desc = "learned (random projection of the 16-d embedding)" if use else "random projection (fallback)"
+        if not use:
+            learned = False
     ws = K.alloc_workspace(kp, K.OP_BUILD, dev)
     ids = torch.empty((w.n, w.k), dtype=torch.int32, device=dev)
     dist = torch.empty((w.n, w.k), dtype=torch.float32, device=dev)
     log(f"workspace {ws.numel() / 2**30:.2f} GiB")
+
+    def step(timed):
+        if learned:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            K.mlp_forward(w.d, part.precision, part.scale, part.params, X_t, Z)   # embedding, in place
+            e1.record()
+            st = K.build_split(kp, X_t, Z, ids, dist, ws, timed=True)
+            st["embed"] = e0.elapsed_time(e1)
+            return st
+        return K.build_timed(kp, X_t, ids, dist, ws)
+
     for i in range(args.warmup):
-        K.build(kp, X_t, ids, dist, ws)
+        step(False)
         torch.cuda.synchronize()
         log(f"warmup {i} done")
 
@@ -158,7 +233,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        stages.append(K.build_timed(kp, X_t, ids, dist, ws))
+        stages.append(step(True))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1000.0 * wall / args.steps
@@ -170,6 +245,7 @@ def main():
     leaf_ms = float(np.mean([s["leaf"] for s in stages]))
     merge_ms = float(np.mean([s["merge"] for s in stages]))
     prop_ms = float(np.mean([sum(s["rounds"]) for s in stages]))
+    embed_ms = float(np.mean([s.get("embed", 0.0) for s in stages]))
     leaf_launch_ms = leaf_ms                       # one persistent launch covers every division's leaves
     flops = [float(sum(leaf_flops(K, kp)))]
     leaf_tflops = (flops[0] / (leaf_launch_ms * 1e-3)) / 1e12
@@ -207,8 +283,7 @@ def main():
         "config": {"workload": w.name, "n": w.n, "d": w.d, "k": w.k, "T": T, "leaf_max": w.leaf_max,
                    "rounds": rounds, "pairwise": True, "leaf_gram": "bf16" if kp.precision == K.BF16 else "fp32",
                    "leaf_cap_cycle": w.leaf_cap_cycle, "split_permille": [w.q_lo_pm, w.q_hi_pm],
-                   "split": "principal direction (16 FP32 power iterations on 256 samples)" if w.split == "pca"
-                   else "random projection"},
+                   "split": split_desc, "rerank_m": w.rerank_m},
         "recall@10": round(rec10, 5),
         "recall_queries": int(len(queries)),
         "roofline": {"kernel": "k_leaf (leaf k-NN of all T divisions, one persistent launch)", "bound": "mfma",
@@ -216,7 +291,7 @@ def main():
                      "frac": round(leaf_tflops / peak, 4), "traffic": traffic,
                      "flop_per_launch": float(np.mean(flops)), "launch_ms": round(leaf_launch_ms, 4)},
         "stages_ms_per_step": {"divide": round(div_ms, 3), "leaf": round(leaf_ms, 3), "merge": round(merge_ms, 3),
-                               "propagate": round(prop_ms, 3)},
+                               "propagate": round(prop_ms, 3), **({"embed": round(embed_ms, 3)} if learned else {})},
         "propagate": {"achieved_GBps": round(prop_gbs, 1), "peak_GBps": PEAK_HBM,
                       "frac": round(prop_gbs / PEAK_HBM, 4), "candidates_per_point": round(U / w.n, 2),
                       "algorithmic_bytes_per_round": prop_bytes},
@@ -224,6 +299,8 @@ def main():
         "paper_context": "single-thread 2.66 GHz CPU, 1M SIFT: ~810-820 points/s at 95% accuracy (derived from "
                          "'about 1% of the brute-force time', Section 4); different data and hardware",
     }
+    if train_info is not None:
+        out["partitioner"] = {"training": train_info, "fallback_rule": choice}
     if args.cpu_sample > 0:
         log(f"cpu baseline on {args.cpu_sample} points")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)

@@ -43,7 +43,8 @@ class Workload:
     q_hi_pm: int = 500
     precision: str = "fp32"      # leaf Gram precision
     rerank_m: int = 6
-    split: str = "rp"            # "rp": random projection; "pca": random principal direction
+    split: str = "rp"            # "rp": random projection; "pca": random principal direction;
+                                 # "learned": random projection of a trained embedding
 
 
 WORKLOADS = {
@@ -62,6 +63,13 @@ WORKLOADS = {
     "gist1m": Workload("gist1m", 1_000_000, 960, 20, 8, 512, 3, "gist", 500, SEED_BASE + 4, split="pca"),
     # SIFT-like at 4M points, fresh clusters.
     "sift4m": Workload("sift4m", 4_000_000, 128, 10, 6, 512, 2, "sift", 4000, SEED_BASE + 5),
+    # Learned division (network trained on the sift1m graph) with the BF16 leaf Gram.
+    "sift1m_learned_bf16": Workload("sift1m_learned_bf16", 1_000_000, 128, 10, 4, 512, 3, "sift", 1000,
+                                    SEED_BASE + 2, precision="bf16", rerank_m=6, split="learned"),
+    "sift1m_learned": Workload("sift1m_learned", 1_000_000, 128, 10, 4, 512, 3, "sift", 1000, SEED_BASE + 2,
+                               split="learned"),
+    "sift4m_learned": Workload("sift4m_learned", 4_000_000, 128, 10, 6, 512, 2, "sift", 4000, SEED_BASE + 5,
+                               split="learned"),
 }
 
 
@@ -87,16 +95,17 @@ def gaussian_mixture(n: int, d: int, clusters: int, seed: int, lo: float = -10.0
     return out
 
 
-def sift_like(n: int, d: int, clusters: int, seed: int) -> np.ndarray:
+def sift_like(n: int, d: int, clusters: int, seed: int, sample_seed: int | None = None) -> np.ndarray:
     """Rectified, rounded mixture: mu_cj ~ U[-32,128], sigma_cj ~ U[5,40];
-    x = clip(round(mu + sigma*N(0,1)), 0, 255), integer values stored as fp32."""
+    x = clip(round(mu + sigma*N(0,1)), 0, 255), integer values stored as fp32.
+    `sample_seed` draws other points from the same clusters (held-out sets)."""
     pr = _param_rng(seed)
     mu = pr.uniform(-32.0, 128.0, size=(clusters, d))
     sg = pr.uniform(5.0, 40.0, size=(clusters, d))
     out = np.empty((n, d), dtype=np.float32)
     for c, s in enumerate(range(0, n, CHUNK)):
         e = min(n, s + CHUNK)
-        r = _chunk_rng(seed, c)
+        r = _chunk_rng(seed if sample_seed is None else sample_seed, c)
         lab = r.integers(0, clusters, size=e - s)
         v = mu[lab] + sg[lab] * r.standard_normal((e - s, d))
         out[s:e] = np.clip(np.rint(v), 0.0, 255.0).astype(np.float32)

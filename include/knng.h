@@ -80,7 +80,8 @@ typedef enum {
   KNNG_OP_LEAF = 1,
   KNNG_OP_MERGE = 2,
   KNNG_OP_PROPAGATE = 3,
-  KNNG_OP_BUILD = 4
+  KNNG_OP_BUILD = 4,
+  KNNG_OP_COLEAF = 5
 } knng_op;
 
 typedef struct {
@@ -186,6 +187,102 @@ int knng_build(const knng_params* p, const float* X, uint32_t* ids, float* dist,
  * exact-row pass), the merge (2), then each propagation round (3 + r).     */
 int knng_build_timed(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
                      void* stream, float* ms_out, int ms_cap);
+
+/* knng_build with the T divisions computed on other rows: point i is placed
+ * in the trees by row i of S (n x ds float32, ds a multiple of 4 with
+ * 4 <= ds <= p->d; p->split applies in R^ds), while the leaf k-NN, the merge
+ * and the propagation measure distances between rows of X.  With S the
+ * embedding of a trained partitioner (knng_mlp_forward) this is the learned
+ * division: random-projection splits of the embedded points.  S = X and
+ * ds = p->d give knng_build exactly.  Workspace: knng_workspace_bytes(p,
+ * KNNG_OP_BUILD).  ms_out may be NULL; otherwise it receives stage times as
+ * in knng_build_timed and the call waits for the stream.                   */
+int knng_build_split(const knng_params* p, const float* X, const float* S, int32_t ds, uint32_t* ids, float* dist,
+                     void* ws, size_t ws_bytes, void* stream, float* ms_out, int ms_cap);
+
+/* Share of n_pairs point pairs (device uint32 [2 n_pairs], pair j =
+ * (pairs[2j], pairs[2j+1])) whose two points land in the same leaf of
+ * division t computed on S (n x ds, as in knng_build_split).  For exact
+ * neighbour pairs this is the single-tree co-leaf probability that Lemma 1
+ * multiplies over trees.  *rate is written on the host; waits for the
+ * stream.  Workspace: knng_workspace_bytes(p, KNNG_OP_COLEAF).             */
+int knng_coleaf_rate(const knng_params* p, int t, const float* S, int32_t ds, const uint32_t* pairs, int64_t n_pairs,
+                     double* rate, void* ws, size_t ws_bytes, void* stream);
+
+/* The learned division's fallback rule: computes the co-leaf rate of the
+ * held-out pairs (knng_coleaf_rate, division 0) for the plain division on X
+ * (p->split in R^d) and for the learned one on Z (random projection in
+ * R^KNNG_MLP_EMB), and sets *use_learned to 1 only if the learned rate is
+ * strictly higher.  Rates are written to the host; waits for the stream.
+ * Workspace: knng_workspace_bytes(p, KNNG_OP_COLEAF).                      */
+int knng_learned_choice(const knng_params* p, const float* X, const float* Z, const uint32_t* pairs, int64_t n_pairs,
+                        int32_t* use_learned, double* rate_plain, double* rate_learned, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned partitioner (an added form of the method; not in the paper).
+ * A two-layer network z = W2 relu(W1 (scale x) + b1) + b2 maps a point of
+ * R^d to R^KNNG_MLP_EMB through KNNG_MLP_HIDDEN hidden units.  Parameters
+ * are one float32 device array of knng_mlp_param_count(d) entries laid out
+ * as W1 [H][d] row-major | b1 [H] | W2 [E][H] row-major | b2 [E].  The
+ * matrix products run on MFMA: KNNG_BF16 rounds both operands to bfloat16
+ * (round to nearest even) and accumulates in float32; KNNG_FP32 keeps
+ * float32 throughout.  d must be a multiple of 16 with 16 <= d <= 256.
+ *
+ * Training minimises the contrastive loss of Hadsell, Chopra and LeCun
+ * (CVPR 2006) over P positive pairs (a, b) and N negative pairs (a, u):
+ *   L = mean_P |z_a - z_b|^2 + lam * mean_N max(0, margin - |z_a - z_u|^2)
+ * with Adam (Kingma and Ba, ICLR 2015).  Positives are edges of a k-NN
+ * graph the method produced, negatives uniform random pairs.
+ * ------------------------------------------------------------------------- */
+#define KNNG_MLP_HIDDEN 256
+#define KNNG_MLP_EMB 16
+
+/* Number of float32 parameters for input dimension d (0 if d is invalid). */
+int64_t knng_mlp_param_count(int32_t d);
+
+/* Initial parameters: W1 ~ U(-sqrt(6/d), sqrt(6/d)), W2 ~ U(-sqrt(6/(H+E)),
+ * sqrt(6/(H+E))) from 24-bit uniforms of the library's counter generator
+ * (tag 4, index = parameter position), biases zero.                        */
+int knng_mlp_init(int32_t d, uint64_t seed, float* params, void* stream);
+
+/* Z (n x KNNG_MLP_EMB float32, 16-byte aligned) = network(X) for n rows. */
+int knng_mlp_forward(int32_t d, int32_t precision, float scale, const float* params, const float* X, int64_t n,
+                     float* Z, void* stream);
+
+/* Workspace for knng_mlp_grad / knng_mlp_train with n_pos + n_neg pairs. */
+size_t knng_mlp_workspace_bytes(int32_t d, int32_t n_pos, int32_t n_neg);
+
+/* Gradient of L with respect to every parameter (grads: param_count
+ * float32, device) and L itself (loss: one float32, device; may be NULL)
+ * for the pairs in rows (device uint32 [2 (n_pos + n_neg)]: pair j =
+ * (rows[2j], rows[2j+1]), positives first).  Per-chunk partial sums are
+ * added in a fixed order, so the result is deterministic.                 */
+int knng_mlp_grad(int32_t d, int32_t precision, float scale, const float* params, const float* X,
+                  const uint32_t* rows, int32_t n_pos, int32_t n_neg, float lam, float margin, float* grads,
+                  float* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* One Adam step (t = step >= 1) on n parameters with moments m, v.        */
+int knng_mlp_adam(int64_t n, float* params, const float* grads, float* m, float* v, int32_t step, float lr,
+                  float beta1, float beta2, float eps, void* stream);
+
+/* Training pairs of step `step` from a k-NN graph ids (n x k): pair j <
+ * n_pos is (i, ids[i][s]) with i, s drawn uniformly; the others (a, b)
+ * uniform over [0, n).  Draw j uses the counter generator with tag 5
+ * (positives) or 6 (negatives), division field step mod 4096, node field j,
+ * index field step / 4096; i = hi32(r) * n >> 32, s = lo32(r) * k >> 32,
+ * b = lo32(r) * n >> 32.  A padded slot (KNNG_NONE) pairs i with itself.  */
+int knng_mlp_sample_pairs(int64_t n, int32_t k, const uint32_t* ids, uint64_t seed, uint32_t step, int32_t n_pos,
+                          int32_t n_neg, uint32_t* rows, void* stream);
+
+/* steps iterations of (sample pairs, gradient, Adam) starting at Adam step
+ * step0 + 1, all enqueued on the stream.  losses (device, steps float32)
+ * receives each step's loss and may be NULL.  Workspace:
+ * knng_mlp_workspace_bytes(d, n_pos, n_neg).                              */
+int knng_mlp_train(int32_t d, int32_t precision, float scale, float* params, float* m, float* v, const float* X,
+                   int64_t n, int32_t k, const uint32_t* graph_ids, uint64_t seed, int32_t step0, int32_t steps,
+                   int32_t n_pos, int32_t n_neg, float lam, float margin, float lr, float* losses, void* ws,
+                   size_t ws_bytes, void* stream);
 
 /* Copies the diagnostics of the last call that used workspace `ws` to the
  * host; waits for `stream`.                                                */

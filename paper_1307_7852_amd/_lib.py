@@ -19,7 +19,8 @@ MAX_LEAF = 2048
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 SPLIT_RP, SPLIT_PCA = 0, 1
 FP32, BF16 = 0, 1
-OP_DIVIDE, OP_LEAF, OP_MERGE, OP_PROPAGATE, OP_BUILD = 0, 1, 2, 3, 4
+OP_DIVIDE, OP_LEAF, OP_MERGE, OP_PROPAGATE, OP_BUILD, OP_COLEAF = 0, 1, 2, 3, 4, 5
+MLP_HIDDEN, MLP_EMB = 256, 16
 
 
 class _CParams(ctypes.Structure):
@@ -79,6 +80,7 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER(_CParams)
     vp, sz, i32, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int64
+    u64, f32 = ctypes.c_uint64, ctypes.c_float
     sig = {
         "knng_status_str": (ctypes.c_char_p, [i32]),
         "knng_last_error": (ctypes.c_char_p, []),
@@ -92,6 +94,19 @@ def _load():
         "knng_build": (i32, [P, vp, vp, vp, vp, sz, vp]),
         "knng_read_diag": (i32, [P, vp, i32, ctypes.POINTER(_CDiag), vp]),
         "knng_build_timed": (i32, [P, vp, vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_float), i32]),
+        "knng_build_split": (i32, [P, vp, vp, i32, vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_float), i32]),
+        "knng_coleaf_rate": (i32, [P, i32, vp, i32, vp, i64, ctypes.POINTER(ctypes.c_double), vp, sz, vp]),
+        "knng_learned_choice": (i32, [P, vp, vp, vp, i64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double), vp, sz, vp]),
+        "knng_mlp_param_count": (i64, [i32]),
+        "knng_mlp_init": (i32, [i32, u64, vp, vp]),
+        "knng_mlp_forward": (i32, [i32, i32, f32, vp, vp, i64, vp, vp]),
+        "knng_mlp_workspace_bytes": (sz, [i32, i32, i32]),
+        "knng_mlp_grad": (i32, [i32, i32, f32, vp, vp, vp, i32, i32, f32, f32, vp, vp, vp, sz, vp]),
+        "knng_mlp_adam": (i32, [i64, vp, vp, vp, vp, i32, f32, f32, f32, f32, vp]),
+        "knng_mlp_sample_pairs": (i32, [i64, i32, vp, u64, ctypes.c_uint32, i32, i32, vp, vp]),
+        "knng_mlp_train": (i32, [i32, i32, f32, vp, vp, vp, vp, i64, i32, vp, u64, i32, i32, i32, i32, f32, f32, f32,
+                                 vp, vp, sz, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -102,7 +117,9 @@ def _load():
 
 _lib = _load()
 EXPORTS = ["knng_status_str", "knng_last_error", "knng_workspace_bytes", "knng_tree_shape", "knng_divide",
-           "knng_leaf_knn", "knng_merge", "knng_propagate", "knng_build", "knng_read_diag", "knng_build_timed"]
+           "knng_leaf_knn", "knng_merge", "knng_propagate", "knng_build", "knng_read_diag", "knng_build_timed",
+           "knng_build_split", "knng_coleaf_rate", "knng_learned_choice", "knng_mlp_param_count", "knng_mlp_init", "knng_mlp_forward",
+           "knng_mlp_workspace_bytes", "knng_mlp_grad", "knng_mlp_adam", "knng_mlp_sample_pairs", "knng_mlp_train"]
 
 
 def _status_name(s: int) -> str:
@@ -185,6 +202,84 @@ def build_timed(p: Params, X, ids, dist, ws, stream=None) -> dict:
                                  ws.numel() * ws.element_size(), _stream(stream), buf, nst))
     v = list(buf)
     return {"divide": v[0], "leaf": v[1], "merge": v[2], "rounds": v[3:]}
+
+
+def build_split(p: Params, X, S, ids, dist, ws, timed: bool = False, stream=None):
+    """Build with divisions computed on the rows of S (n x ds); with timed,
+    returns per-stage GPU times as build_timed does."""
+    cp = p.c()
+    nst = 3 + p.rounds
+    buf = (ctypes.c_float * nst)() if timed else None
+    _check(_lib.knng_build_split(ctypes.byref(cp), _ptr(X), _ptr(S), int(S.shape[1]), _ptr(ids), _ptr(dist), _ptr(ws),
+                                 ws.numel() * ws.element_size(), _stream(stream), buf, nst if timed else 0))
+    if timed:
+        v = list(buf)
+        return {"divide": v[0], "leaf": v[1], "merge": v[2], "rounds": v[3:]}
+    return None
+
+
+def coleaf_rate(p: Params, t: int, S, pairs, ws, stream=None) -> float:
+    """Share of the pairs (uint32 tensor (m, 2)) that share a leaf of division t built on S."""
+    cp = p.c()
+    out = ctypes.c_double()
+    _check(_lib.knng_coleaf_rate(ctypes.byref(cp), t, _ptr(S), int(S.shape[1]), _ptr(pairs), int(pairs.shape[0]),
+                                 ctypes.byref(out), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+    return out.value
+
+
+def learned_choice(p: Params, X, Z, pairs, ws, stream=None):
+    """(use_learned, rate_plain, rate_learned) of the fallback rule."""
+    cp = p.c()
+    use, rp, rl = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+    _check(_lib.knng_learned_choice(ctypes.byref(cp), _ptr(X), _ptr(Z), _ptr(pairs), int(pairs.shape[0]),
+                                    ctypes.byref(use), ctypes.byref(rp), ctypes.byref(rl), _ptr(ws),
+                                    ws.numel() * ws.element_size(), _stream(stream)))
+    return bool(use.value), rp.value, rl.value
+
+
+def mlp_param_count(d: int) -> int:
+    n = _lib.knng_mlp_param_count(d)
+    if n == 0:
+        raise KnngError(EINVAL, _lib.knng_last_error().decode())
+    return n
+
+
+def mlp_init(d: int, seed: int, params, stream=None):
+    _check(_lib.knng_mlp_init(d, seed, _ptr(params), _stream(stream)))
+
+
+def mlp_forward(d: int, precision: int, scale: float, params, X, Z, stream=None):
+    _check(_lib.knng_mlp_forward(d, precision, scale, _ptr(params), _ptr(X), int(X.shape[0]), _ptr(Z),
+                                 _stream(stream)))
+
+
+def mlp_workspace_bytes(d: int, n_pos: int, n_neg: int) -> int:
+    n = _lib.knng_mlp_workspace_bytes(d, n_pos, n_neg)
+    if n == 0:
+        raise KnngError(EINVAL, _lib.knng_last_error().decode())
+    return n
+
+
+def mlp_grad(d: int, precision: int, scale: float, params, X, rows, n_pos: int, n_neg: int, lam: float, margin: float,
+             grads, loss, ws, stream=None):
+    _check(_lib.knng_mlp_grad(d, precision, scale, _ptr(params), _ptr(X), _ptr(rows), n_pos, n_neg, lam, margin,
+                              _ptr(grads), _ptr(loss), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def mlp_adam(params, grads, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(_lib.knng_mlp_adam(params.numel(), _ptr(params), _ptr(grads), _ptr(m), _ptr(v), step, lr, beta1, beta2, eps,
+                              _stream(stream)))
+
+
+def mlp_sample_pairs(n: int, k: int, ids, seed: int, step: int, n_pos: int, n_neg: int, rows, stream=None):
+    _check(_lib.knng_mlp_sample_pairs(n, k, _ptr(ids), seed, step, n_pos, n_neg, _ptr(rows), _stream(stream)))
+
+
+def mlp_train(d: int, precision: int, scale: float, params, m, v, X, k: int, graph_ids, seed: int, step0: int,
+              steps: int, n_pos: int, n_neg: int, lam: float, margin: float, lr: float, losses, ws, stream=None):
+    _check(_lib.knng_mlp_train(d, precision, scale, _ptr(params), _ptr(m), _ptr(v), _ptr(X), int(X.shape[0]), k,
+                               _ptr(graph_ids), seed, step0, steps, n_pos, n_neg, lam, margin, lr, _ptr(losses),
+                               _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def read_diag(p: Params, ws, op: int, stream=None) -> dict:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -311,6 +312,24 @@ int build_layout(const knng_params& p, BuildLayout& L) {
   return KNNG_OK;
 }
 
+// knng_coleaf_rate: perm | leaf offsets | labels | count | knng_divide workspace
+struct ColeafLayout { size_t perm, leaf_off, label, count, divide, total; };
+int coleaf_layout(const knng_params& p, int t, ColeafLayout& L) {
+  DivideLayout D;
+  int st = divide_layout(p, t, D);
+  if (st) return st;
+  PlanPtr pl = get_plan(p, t, &st);
+  if (!pl) return st;
+  Carve c;
+  L.perm = c.take((size_t)p.n * 4);
+  L.leaf_off = c.take(pl->leaf_off.size() * 8);
+  L.label = c.take((size_t)p.n * 4);
+  L.count = c.take(16);
+  L.divide = c.take(D.total);
+  L.total = c.off;
+  return KNNG_OK;
+}
+
 hipError_t zero_diag(void* diag, hipStream_t s) {
   return launch_fill_u32((uint32_t*)diag, 0u, sizeof(DiagDev) / 4, s);
 }
@@ -568,6 +587,15 @@ size_t knng_workspace_bytes(const knng_params* p, int op) {
       if (build_layout(*p, L) != KNNG_OK) return 0;
       return L.total;
     }
+    case KNNG_OP_COLEAF: {
+      size_t mx = 0;
+      for (int t = 0; t < p->T; ++t) {
+        ColeafLayout L;
+        if (coleaf_layout(*p, t, L) != KNNG_OK) return 0;
+        mx = std::max(mx, L.total);
+      }
+      return mx;
+    }
     default: fail(KNNG_EINVAL, "unknown op %d", op); return 0;
   }
 }
@@ -665,12 +693,15 @@ int knng_propagate(const knng_params* p, const float* X, uint32_t* ids, float* d
 // division; the T lists are merged; the rounds run with points visited in
 // division 0's leaf order (neighbouring points share candidates, so their
 // rows stay in cache).
-static int build_impl(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
-                      void* stream, std::vector<hipEvent_t>* ev) {
+static int build_impl(const knng_params* p, const float* X, const float* S, int ds, uint32_t* ids, float* dist,
+                      void* ws, size_t ws_bytes, void* stream, std::vector<hipEvent_t>* ev) {
   int st = validate(p);
   if (st) return st;
-  if (!X || !ids || !dist || !ws) return fail(KNNG_EINVAL, "null array argument");
-  if (!aligned16(X)) return fail(KNNG_EINVAL, "X must be 16-byte aligned");
+  if (!X || !S || !ids || !dist || !ws) return fail(KNNG_EINVAL, "null array argument");
+  if (!aligned16(X) || !aligned16(S)) return fail(KNNG_EINVAL, "X and S must be 16-byte aligned");
+  if (ds < 4 || ds > p->d || ds % 4 != 0) return fail(KNNG_EINVAL, "ds=%d must be a multiple of 4 in [4, d]", ds);
+  knng_params ps = *p;   // the divisions see rows of S
+  ps.d = ds;
   if (((uintptr_t)ws & 255) != 0) return fail(KNNG_EINVAL, "ws must be 256-byte aligned");
   if ((int64_t)p->T * p->k > 1024) return fail(KNNG_EUNSUPPORTED, "T * k = %d exceeds 1024", p->T * p->k);
   if (p->rounds > 0 && p->k > 31) return fail(KNNG_EUNSUPPORTED, "propagation supports k <= 31 (got %d)", p->k);
@@ -693,7 +724,7 @@ static int build_impl(const knng_params* p, const float* X, uint32_t* ids, float
   float* lists_dist = (float*)(w + BL.lists_dist);
   char* sh = w + BL.shared;
   HIP_TRY(mark(0));
-  st = divide_core(*p, *B, w + BL.blob, X, nullptr, nullptr, permA, permB, sh, s);
+  st = divide_core(ps, *B, w + BL.blob, S, nullptr, nullptr, permA, permB, sh, s);
   if (st) return st;
   const uint32_t* perms = (B->depth % 2 == 0) ? permA : permB;
   HIP_TRY(mark(1));
@@ -711,11 +742,12 @@ static int build_impl(const knng_params* p, const float* X, uint32_t* ids, float
 
 int knng_build(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
                void* stream) {
-  return build_impl(p, X, ids, dist, ws, ws_bytes, stream, nullptr);
+  if (!p) return fail(KNNG_EINVAL, "null params");
+  return build_impl(p, X, X, p->d, ids, dist, ws, ws_bytes, stream, nullptr);
 }
 
-int knng_build_timed(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
-                     void* stream, float* ms_out, int ms_cap) {
+static int build_timed_impl(const knng_params* p, const float* X, const float* S, int ds, uint32_t* ids, float* dist,
+                            void* ws, size_t ws_bytes, void* stream, float* ms_out, int ms_cap) {
   int st = validate(p);
   if (st) return st;
   int nst = 3 + p->rounds;
@@ -726,7 +758,7 @@ int knng_build_timed(const knng_params* p, const float* X, uint32_t* ids, float*
       for (auto& f : ev) if (f) (void)hipEventDestroy(f);
       return fail(KNNG_EHIP, "hipEventCreate failed");
     }
-  st = build_impl(p, X, ids, dist, ws, ws_bytes, stream, &ev);
+  st = build_impl(p, X, S, ds, ids, dist, ws, ws_bytes, stream, &ev);
   if (st == KNNG_OK) {
     hipError_t e = hipEventSynchronize(ev[nst]);
     for (int i = 0; i < nst && e == hipSuccess; ++i) e = hipEventElapsedTime(&ms_out[i], ev[i], ev[i + 1]);
@@ -734,6 +766,70 @@ int knng_build_timed(const knng_params* p, const float* X, uint32_t* ids, float*
   }
   for (auto& f : ev) (void)hipEventDestroy(f);
   return st;
+}
+
+int knng_build_timed(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
+                     void* stream, float* ms_out, int ms_cap) {
+  if (!p) return fail(KNNG_EINVAL, "null params");
+  return build_timed_impl(p, X, X, p->d, ids, dist, ws, ws_bytes, stream, ms_out, ms_cap);
+}
+
+int knng_build_split(const knng_params* p, const float* X, const float* S, int32_t ds, uint32_t* ids, float* dist,
+                     void* ws, size_t ws_bytes, void* stream, float* ms_out, int ms_cap) {
+  if (!ms_out) return build_impl(p, X, S, ds, ids, dist, ws, ws_bytes, stream, nullptr);
+  return build_timed_impl(p, X, S, ds, ids, dist, ws, ws_bytes, stream, ms_out, ms_cap);
+}
+
+int knng_coleaf_rate(const knng_params* p, int t, const float* S, int32_t ds, const uint32_t* pairs, int64_t n_pairs,
+                     double* rate, void* ws, size_t ws_bytes, void* stream) {
+  int st = validate(p);
+  if (st) return st;
+  if (t < 0 || t >= 4096) return fail(KNNG_EINVAL, "t=%d out of [0, 4096)", t);
+  if (!S || !rate || !ws || (n_pairs > 0 && !pairs)) return fail(KNNG_EINVAL, "null argument");
+  if (n_pairs < 0) return fail(KNNG_EINVAL, "n_pairs=%lld < 0", (long long)n_pairs);
+  if (!aligned16(S)) return fail(KNNG_EINVAL, "S must be 16-byte aligned");
+  if (ds < 4 || ds > p->d || ds % 4 != 0) return fail(KNNG_EINVAL, "ds=%d must be a multiple of 4 in [4, d]", ds);
+  if (((uintptr_t)ws & 255) != 0) return fail(KNNG_EINVAL, "ws must be 256-byte aligned");
+  knng_params ps = *p;
+  ps.d = ds;
+  ColeafLayout L;
+  st = coleaf_layout(*p, t, L);
+  if (st) return st;
+  if (ws_bytes < L.total) return fail(KNNG_ENOMEM, "coleaf needs %zu workspace bytes, got %zu", L.total, ws_bytes);
+  char* w = (char*)ws;
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t* perm = (uint32_t*)(w + L.perm);
+  int64_t* leaf_off = (int64_t*)(w + L.leaf_off);
+  st = knng_divide(&ps, t, S, nullptr, nullptr, perm, leaf_off, w + L.divide, ws_bytes - L.divide, stream);
+  if (st) return st;
+  int64_t n_leaves = 0, n_int = 0;
+  int32_t depth = 0;
+  st = knng_tree_shape(p, t, nullptr, 0, &n_leaves, &n_int, &depth);
+  if (st) return st;
+  unsigned long long* count = (unsigned long long*)(w + L.count);
+  HIP_TRY(launch_coleaf(perm, leaf_off, n_leaves, (uint32_t*)(w + L.label), pairs, n_pairs, count, s));
+  unsigned long long hc = 0;
+  HIP_TRY(hipMemcpyAsync(&hc, count, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *rate = n_pairs > 0 ? (double)hc / (double)n_pairs : 0.0;
+  return KNNG_OK;
+}
+
+int knng_learned_choice(const knng_params* p, const float* X, const float* Z, const uint32_t* pairs, int64_t n_pairs,
+                        int32_t* use_learned, double* rate_plain, double* rate_learned, void* ws, size_t ws_bytes,
+                        void* stream) {
+  int st = validate(p);
+  if (st) return st;
+  if (!use_learned || !rate_plain || !rate_learned) return fail(KNNG_EINVAL, "null output pointer");
+  if (p->d < KNNG_MLP_EMB) return fail(KNNG_EINVAL, "d=%d below the embedding width %d", p->d, KNNG_MLP_EMB);
+  st = knng_coleaf_rate(p, 0, X, p->d, pairs, n_pairs, rate_plain, ws, ws_bytes, stream);
+  if (st) return st;
+  knng_params pl = *p;
+  pl.split = KNNG_SPLIT_RP;
+  st = knng_coleaf_rate(&pl, 0, Z, KNNG_MLP_EMB, pairs, n_pairs, rate_learned, ws, ws_bytes, stream);
+  if (st) return st;
+  *use_learned = *rate_learned > *rate_plain ? 1 : 0;
+  return KNNG_OK;
 }
 
 int knng_read_diag(const knng_params* p, const void* ws, int op, knng_diag* out, void* stream) {
@@ -750,6 +846,167 @@ int knng_read_diag(const knng_params* p, const void* ws, int op, knng_diag* out,
   for (int i = 0; i < DIAG_SLOTS; ++i) {
     out->prop_candidates += (int64_t)d.prop_candidates[i];
     out->prop_proposals += (int64_t)d.prop_proposals[i];
+  }
+  return KNNG_OK;
+}
+
+// ------------------------------------------------------------------ learned partitioner
+static int mlp_check_d(int32_t d) {
+  if (d < 16 || d > 256 || d % 16 != 0) return fail(KNNG_EINVAL, "MLP input dimension d=%d must be a multiple of 16 in [16, 256]", d);
+  return KNNG_OK;
+}
+
+int64_t knng_mlp_param_count(int32_t d) {
+  if (mlp_check_d(d)) return 0;
+  return (int64_t)KNNG_MLP_HIDDEN * d + KNNG_MLP_HIDDEN + (int64_t)KNNG_MLP_EMB * KNNG_MLP_HIDDEN + KNNG_MLP_EMB;
+}
+
+int knng_mlp_init(int32_t d, uint64_t seed, float* params, void* stream) {
+  int st = mlp_check_d(d);
+  if (st) return st;
+  if (!params || !aligned16(params)) return fail(KNNG_EINVAL, "params must be non-null and 16-byte aligned");
+  const float lim1 = (float)std::sqrt(6.0 / d);
+  const float lim2 = (float)std::sqrt(6.0 / (KNNG_MLP_HIDDEN + KNNG_MLP_EMB));
+  HIP_TRY(launch_mlp_init(params, d, seed, lim1, lim2, (hipStream_t)stream));
+  return KNNG_OK;
+}
+
+int knng_mlp_forward(int32_t d, int32_t precision, float scale, const float* params, const float* X, int64_t n,
+                     float* Z, void* stream) {
+  int st = mlp_check_d(d);
+  if (st) return st;
+  if (precision != KNNG_FP32 && precision != KNNG_BF16) return fail(KNNG_EINVAL, "precision=%d", precision);
+  if (n < 0) return fail(KNNG_EINVAL, "n=%lld < 0", (long long)n);
+  if (n == 0) return KNNG_OK;
+  if (!params || !X || !Z) return fail(KNNG_EINVAL, "null array argument");
+  if (!aligned16(params) || !aligned16(X) || !aligned16(Z)) return fail(KNNG_EINVAL, "arrays must be 16-byte aligned");
+  MlpArgs a{};
+  a.params = params; a.X = X; a.d = d; a.scale = scale; a.bf16 = precision == KNNG_BF16;
+  a.rows = nullptr; a.R = n; a.Z = Z;
+  HIP_TRY(launch_mlp_forward(a, false, (hipStream_t)stream));
+  return KNNG_OK;
+}
+
+namespace {
+constexpr int64_t MLP_CHUNK_ROWS = 512;
+// Z | Hs | dZ | dA | loss parts | chunk partials | grads | rows | loss
+struct MlpLayout { size_t Z, Hs, dZ, dA, lpart, part, grads, rows, loss, total; int64_t R, chunks, P; int nlp; };
+MlpLayout mlp_layout(int d, int n_pos, int n_neg) {
+  MlpLayout L{};
+  L.R = 2 * ((int64_t)n_pos + n_neg);
+  L.chunks = (L.R + MLP_CHUNK_ROWS - 1) / MLP_CHUNK_ROWS;
+  L.P = (int64_t)KNNG_MLP_HIDDEN * d + KNNG_MLP_HIDDEN + (int64_t)KNNG_MLP_EMB * KNNG_MLP_HIDDEN + KNNG_MLP_EMB;
+  L.nlp = (int)((n_pos + (int64_t)n_neg + 255) / 256);
+  Carve c;
+  L.Z = c.take((size_t)L.R * KNNG_MLP_EMB * 4);
+  L.Hs = c.take((size_t)L.R * KNNG_MLP_HIDDEN * 4);
+  L.dZ = c.take((size_t)L.R * KNNG_MLP_EMB * 4);
+  L.dA = c.take((size_t)L.R * KNNG_MLP_HIDDEN * 4);
+  L.lpart = c.take((size_t)std::max(1, L.nlp) * 4);
+  L.part = c.take((size_t)std::max<int64_t>(1, L.chunks) * L.P * 4);
+  L.grads = c.take((size_t)L.P * 4);
+  L.rows = c.take((size_t)L.R * 4);
+  L.loss = c.take(4);
+  L.total = c.off;
+  return L;
+}
+
+int mlp_grad_core(int32_t d, int32_t precision, float scale, const float* params, const float* X, const uint32_t* rows,
+                  int32_t n_pos, int32_t n_neg, float lam, float margin, float* grads, float* loss, char* w,
+                  const MlpLayout& L, hipStream_t s) {
+  MlpArgs a{};
+  a.params = params; a.X = X; a.d = d; a.scale = scale; a.bf16 = precision == KNNG_BF16;
+  a.rows = rows; a.R = L.R;
+  a.Z = (float*)(w + L.Z); a.Hs = (float*)(w + L.Hs); a.dZ = (float*)(w + L.dZ); a.dA = (float*)(w + L.dA);
+  a.n_pos = n_pos; a.n_neg = n_neg; a.lam = lam; a.margin = margin;
+  a.loss_part = (float*)(w + L.lpart); a.n_loss_parts = L.nlp; a.loss = loss;
+  a.part = (float*)(w + L.part); a.n_chunks = (int)L.chunks; a.chunk_rows = MLP_CHUNK_ROWS; a.n_params = L.P;
+  a.grads = grads;
+  HIP_TRY(launch_mlp_forward(a, true, s));
+  HIP_TRY(launch_mlp_backward(a, s));
+  return KNNG_OK;
+}
+
+int mlp_pairs_check(int32_t n_pos, int32_t n_neg) {
+  if (n_pos < 0 || n_neg < 0 || n_pos + (int64_t)n_neg < 1 || n_pos + (int64_t)n_neg > (1 << 24))
+    return fail(KNNG_EINVAL, "need n_pos, n_neg >= 0 and 1 <= n_pos + n_neg <= 2^24 (got %d, %d)", n_pos, n_neg);
+  return KNNG_OK;
+}
+}  // namespace
+
+size_t knng_mlp_workspace_bytes(int32_t d, int32_t n_pos, int32_t n_neg) {
+  if (mlp_check_d(d) || mlp_pairs_check(n_pos, n_neg)) return 0;
+  return mlp_layout(d, n_pos, n_neg).total;
+}
+
+int knng_mlp_grad(int32_t d, int32_t precision, float scale, const float* params, const float* X,
+                  const uint32_t* rows, int32_t n_pos, int32_t n_neg, float lam, float margin, float* grads,
+                  float* loss, void* ws, size_t ws_bytes, void* stream) {
+  int st = mlp_check_d(d);
+  if (st) return st;
+  if ((st = mlp_pairs_check(n_pos, n_neg))) return st;
+  if (precision != KNNG_FP32 && precision != KNNG_BF16) return fail(KNNG_EINVAL, "precision=%d", precision);
+  if (!params || !X || !rows || !grads || !ws) return fail(KNNG_EINVAL, "null array argument");
+  if (!aligned16(params) || !aligned16(X)) return fail(KNNG_EINVAL, "params and X must be 16-byte aligned");
+  if (((uintptr_t)ws & 255) != 0) return fail(KNNG_EINVAL, "ws must be 256-byte aligned");
+  MlpLayout L = mlp_layout(d, n_pos, n_neg);
+  if (ws_bytes < L.total) return fail(KNNG_ENOMEM, "mlp_grad needs %zu workspace bytes, got %zu", L.total, ws_bytes);
+  return mlp_grad_core(d, precision, scale, params, X, rows, n_pos, n_neg, lam, margin, grads, loss, (char*)ws, L,
+                       (hipStream_t)stream);
+}
+
+int knng_mlp_adam(int64_t n, float* params, const float* grads, float* m, float* v, int32_t step, float lr,
+                  float beta1, float beta2, float eps, void* stream) {
+  if (n < 1) return fail(KNNG_EINVAL, "n=%lld < 1", (long long)n);
+  if (step < 1) return fail(KNNG_EINVAL, "step=%d < 1", step);
+  if (!params || !grads || !m || !v) return fail(KNNG_EINVAL, "null array argument");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
+    return fail(KNNG_EINVAL, "need 0 <= beta1, beta2 < 1 and eps > 0");
+  const float bc1 = (float)(1.0 - std::pow((double)beta1, step));
+  const float bc2 = (float)(1.0 - std::pow((double)beta2, step));
+  HIP_TRY(launch_mlp_adam(params, grads, m, v, n, lr, beta1, beta2, eps, bc1, bc2, (hipStream_t)stream));
+  return KNNG_OK;
+}
+
+int knng_mlp_sample_pairs(int64_t n, int32_t k, const uint32_t* ids, uint64_t seed, uint32_t step, int32_t n_pos,
+                          int32_t n_neg, uint32_t* rows, void* stream) {
+  if (n < 1 || n >= (int64_t)0xFFFFFFFF) return fail(KNNG_EINVAL, "n=%lld out of [1, 2^32 - 1)", (long long)n);
+  if (k < 1) return fail(KNNG_EINVAL, "k=%d < 1", k);
+  int st = mlp_pairs_check(n_pos, n_neg);
+  if (st) return st;
+  if (step >= (1u << 28)) return fail(KNNG_EINVAL, "step=%u >= 2^28", step);
+  if (!rows || (n_pos > 0 && !ids)) return fail(KNNG_EINVAL, "null array argument");
+  HIP_TRY(launch_mlp_sample(ids, n, k, seed, step, n_pos, n_neg, rows, (hipStream_t)stream));
+  return KNNG_OK;
+}
+
+int knng_mlp_train(int32_t d, int32_t precision, float scale, float* params, float* m, float* v, const float* X,
+                   int64_t n, int32_t k, const uint32_t* graph_ids, uint64_t seed, int32_t step0, int32_t steps,
+                   int32_t n_pos, int32_t n_neg, float lam, float margin, float lr, float* losses, void* ws,
+                   size_t ws_bytes, void* stream) {
+  int st = mlp_check_d(d);
+  if (st) return st;
+  if ((st = mlp_pairs_check(n_pos, n_neg))) return st;
+  if (precision != KNNG_FP32 && precision != KNNG_BF16) return fail(KNNG_EINVAL, "precision=%d", precision);
+  if (step0 < 0 || steps < 0 || (int64_t)step0 + steps >= (1 << 28)) return fail(KNNG_EINVAL, "step range out of [0, 2^28)");
+  if (n < 1 || n >= (int64_t)0xFFFFFFFF || k < 1) return fail(KNNG_EINVAL, "need 1 <= n < 2^32 - 1 and k >= 1");
+  if (!params || !m || !v || !X || !graph_ids || !ws) return fail(KNNG_EINVAL, "null array argument");
+  if (!aligned16(params) || !aligned16(X)) return fail(KNNG_EINVAL, "params and X must be 16-byte aligned");
+  if (((uintptr_t)ws & 255) != 0) return fail(KNNG_EINVAL, "ws must be 256-byte aligned");
+  MlpLayout L = mlp_layout(d, n_pos, n_neg);
+  if (ws_bytes < L.total) return fail(KNNG_ENOMEM, "mlp_train needs %zu workspace bytes, got %zu", L.total, ws_bytes);
+  char* w = (char*)ws;
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t* rows = (uint32_t*)(w + L.rows);
+  float* grads = (float*)(w + L.grads);
+  for (int32_t i = 0; i < steps; ++i) {
+    const int32_t step = step0 + i + 1;
+    HIP_TRY(launch_mlp_sample(graph_ids, n, k, seed, (uint32_t)step, n_pos, n_neg, rows, s));
+    st = mlp_grad_core(d, precision, scale, params, X, rows, n_pos, n_neg, lam, margin, grads,
+                       losses ? losses + i : (float*)(w + L.loss), w, L, s);
+    if (st) return st;
+    st = knng_mlp_adam(L.P, params, grads, m, v, step, lr, 0.9f, 0.999f, 1e-8f, stream);
+    if (st) return st;
   }
   return KNNG_OK;
 }

@@ -14,7 +14,7 @@ namespace knng {
 // Counter-based generator: the SplitMix64 finaliser (Steele, Lea & Flood,
 // OOPSLA 2014) applied to the seed xor a mixed counter.  Counter fields:
 // tag (4 bits) | division t (12) | heap node id v (32) | index j (16).
-enum : uint32_t { TAG_DIR = 1, TAG_SPLIT = 2, TAG_SAMPLE = 3 };
+enum : uint32_t { TAG_DIR = 1, TAG_SPLIT = 2, TAG_SAMPLE = 3, TAG_MLP_INIT = 4, TAG_MLP_POS = 5, TAG_MLP_NEG = 6 };
 
 __host__ __device__ inline uint64_t mix64(uint64_t z) {
   z ^= z >> 30;
@@ -159,5 +159,42 @@ struct PropArgs {
   DiagDev* diag;
 };
 hipError_t launch_propagate_round(const PropArgs& a, hipStream_t s);
+
+// ------------------------------------------------------------------ learned partitioner
+// Batch rows 2p, 2p+1 hold pair p (positives first).  Buffers: Z, dZ [R][E];
+// Hs (relu outputs), dA (their gradients) [R][H]; part [n_chunks][n_params].
+struct MlpArgs {
+  const float* params;   // W1 [H][d] | b1 [H] | W2 [E][H] | b2 [E]
+  const float* X;
+  int d;
+  float scale;
+  bool bf16;
+  const uint32_t* rows;  // batch row -> point id (nullptr: row i is point i)
+  int64_t R;
+  float* Z;
+  float* Hs;
+  float* dZ;
+  float* dA;
+  int n_pos, n_neg;
+  float lam, margin;
+  float* loss_part;
+  int n_loss_parts;
+  float* loss;           // device scalar (nullable)
+  float* part;
+  int n_chunks;
+  int64_t chunk_rows;
+  int64_t n_params;
+  float* grads;
+};
+size_t mlp_wgrad_lds(int d);
+hipError_t launch_mlp_forward(const MlpArgs& a, bool train, hipStream_t s);
+hipError_t launch_mlp_backward(const MlpArgs& a, hipStream_t s);
+hipError_t launch_mlp_adam(float* params, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                           float eps, float bc1, float bc2, hipStream_t s);
+hipError_t launch_mlp_init(float* params, int d, uint64_t seed, float lim1, float lim2, hipStream_t s);
+hipError_t launch_mlp_sample(const uint32_t* ids, int64_t n, int k, uint64_t seed, uint32_t step, int n_pos, int n_neg,
+                             uint32_t* rows, hipStream_t s);
+hipError_t launch_coleaf(const uint32_t* perm, const int64_t* leaf_off, int64_t n_leaves, uint32_t* label,
+                         const uint32_t* pairs, int64_t np, unsigned long long* count, hipStream_t s);
 
 }  // namespace knng

@@ -73,3 +73,56 @@ def test_co_leaf_rate():
     off = np.array([0, 2, 4])
     pairs = np.array([[3, 1], [0, 2], [3, 0], [1, 2]])
     assert M.co_leaf_rate(perm, off, pairs) == 0.5
+
+
+def test_bf16_rounding_against_torch_and_ties():
+    import torch
+    rng = np.random.default_rng(1)
+    a = np.concatenate([rng.standard_normal(20000) * 1e3, rng.uniform(-1, 1, 20000) * 1e-30])
+    ref = torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(M.bf16(a), ref)
+    # integers below 256 have at most 8 significant bits: exact
+    ints = np.arange(0, 256, dtype=np.float64)
+    assert np.array_equal(M.bf16(ints), ints)
+    # ties go to even: 1 + 2^-8 lies halfway between 1 and 1 + 2^-7
+    assert M.bf16(np.array([1.0 + 2.0 ** -8]))[0] == 1.0
+    assert M.bf16(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6
+
+
+def test_init_counter_definition():
+    from oracle.knng_oracle import rand64
+    d, seed = 32, 99
+    v = M.init_counter(d, seed)
+    P = M.unflatten(v, d)
+    lim1, lim2 = np.sqrt(6.0 / d), np.sqrt(6.0 / 272)
+    assert np.all(np.abs(P["W1"]) <= lim1) and np.all(np.abs(P["W2"]) <= lim2)
+    assert np.all(P["b1"] == 0) and np.all(P["b2"] == 0)
+    # element i of W1, recomputed in double precision: (2u - 1) is exact and the
+    # product of two float32 values is exact in double, so one rounding remains
+    for i in (0, 1, 1000):
+        u = (rand64(seed, 4, 0, i, 0) >> 40) * 2.0 ** -24
+        assert v[i] == np.float32((2 * u - 1) * float(np.float32(lim1)))
+    o2 = 256 * d + 256
+    u = (rand64(seed, 4, 0, o2, 0) >> 40) * 2.0 ** -24
+    assert v[o2] == np.float32((2 * u - 1) * float(np.float32(lim2)))
+    assert abs(P["W1"].mean()) < 0.02 * lim1 * 10
+
+
+def test_flatten_roundtrip():
+    P = M.init_params(16, 256, 16, 3)
+    Q = M.unflatten(M.flatten(P), 16)
+    for key in P:
+        assert np.array_equal(P[key], Q[key])
+
+
+def test_sample_pairs_definition():
+    rng = np.random.default_rng(2)
+    n, k = 500, 6
+    ids = rng.integers(0, n, size=(n, k)).astype(np.int64)
+    ids[3, :] = 0xFFFFFFFF
+    pr = M.sample_pairs(ids, n, k, seed=5, step=7, n_pos=300, n_neg=200)
+    assert pr.shape == (500, 2) and pr.min() >= 0 and pr.max() < n
+    for i, b in pr[:300]:
+        assert b in set(ids[i]) or (b == i and (ids[i] == 0xFFFFFFFF).any())
+    assert np.array_equal(pr, M.sample_pairs(ids, n, k, 5, 7, 300, 200))
+    assert not np.array_equal(pr, M.sample_pairs(ids, n, k, 5, 8, 300, 200))
