@@ -178,7 +178,7 @@ def main():
     kp = K.Params(n=w.n, d=w.d, k=w.k, T=T, leaf_max=w.leaf_max, leaf_cap_cycle=w.leaf_cap_cycle,
                   q_lo_pm=w.q_lo_pm, q_hi_pm=w.q_hi_pm, rounds=rounds, pairwise=1,
                   precision=K.BF16 if w.precision == "bf16" else K.FP32, rerank_m=w.rerank_m, seed=w.seed + 1,
-                  split=K.SPLIT_PCA if w.split == "pca" else K.SPLIT_RP, pca_iters=16)
+                  split=K.SPLIT_PCA if w.split in ("pca", "learned") else K.SPLIT_RP, pca_iters=16)
     X_t = torch.from_numpy(X).to(dev)
     if args.calibrate_copy:
         src = torch.ones(2 ** 28, dtype=torch.float32, device=dev)
@@ -198,15 +198,17 @@ def main():
         # fallback rule on held-out exact neighbour pairs (not the recall queries)
         hq = datagen.query_sample(w.n, 300, w.seed + 77)
         hp = np.stack([np.repeat(hq, w.k), exact_ids(X, hq, w.k).reshape(-1)], 1)
-        kpc = K.Params(n=w.n, d=w.d, k=w.k, T=1, leaf_max=w.leaf_max, seed=w.seed + 1)
+        kpc = K.Params(n=w.n, d=w.d, k=w.k, T=1, leaf_max=w.leaf_max, seed=w.seed + 1, split=K.SPLIT_PCA)
         use, r_plain, r_learned = K.learned_choice(kpc, X_t, Z, torch.from_numpy(hp.astype(np.int32)).to(dev),
                                                    K.alloc_workspace(kpc, K.OP_COLEAF, dev))
         choice = {"use_learned": use, "coleaf_plain_rp": round(r_plain, 4), "coleaf_learned": round(r_learned, 4),
                   "held_out_pairs": int(len(hp))}
         log(f"  fallback rule: {choice}")
-        split_desc = "learned (random projection of the 16-d embedding)" if use else "random projection (fallback)"
+        split_desc = ("learned (principal direction of the 16-d embedding, 16 FP32 power iterations)" if use
+                      else "random projection (fallback)")
         if not use:
             learned = False
+            kp.split = K.SPLIT_RP
     ws = K.alloc_workspace(kp, K.OP_BUILD, dev)
     ids = torch.empty((w.n, w.k), dtype=torch.int32, device=dev)
     dist = torch.empty((w.n, w.k), dtype=torch.float32, device=dev)

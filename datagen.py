@@ -44,7 +44,7 @@ class Workload:
     precision: str = "fp32"      # leaf Gram precision
     rerank_m: int = 6
     split: str = "rp"            # "rp": random projection; "pca": random principal direction;
-                                 # "learned": random projection of a trained embedding
+                                 # "learned": principal direction of a trained embedding
 
 
 WORKLOADS = {
@@ -64,9 +64,9 @@ WORKLOADS = {
     # SIFT-like at 4M points, fresh clusters.
     "sift4m": Workload("sift4m", 4_000_000, 128, 10, 6, 512, 2, "sift", 4000, SEED_BASE + 5),
     # Learned division (network trained on the sift1m graph) with the BF16 leaf Gram.
-    "sift1m_learned_bf16": Workload("sift1m_learned_bf16", 1_000_000, 128, 10, 4, 512, 3, "sift", 1000,
+    "sift1m_learned_bf16": Workload("sift1m_learned_bf16", 1_000_000, 128, 10, 8, 512, 1, "sift", 1000,
                                     SEED_BASE + 2, precision="bf16", rerank_m=6, split="learned"),
-    "sift1m_learned": Workload("sift1m_learned", 1_000_000, 128, 10, 4, 512, 3, "sift", 1000, SEED_BASE + 2,
+    "sift1m_learned": Workload("sift1m_learned", 1_000_000, 128, 10, 8, 512, 1, "sift", 1000, SEED_BASE + 2,
                                split="learned"),
     "sift4m_learned": Workload("sift4m_learned", 4_000_000, 128, 10, 6, 512, 2, "sift", 4000, SEED_BASE + 5,
                                split="learned"),

@@ -210,11 +210,12 @@ int knng_coleaf_rate(const knng_params* p, int t, const float* S, int32_t ds, co
                      double* rate, void* ws, size_t ws_bytes, void* stream);
 
 /* The learned division's fallback rule: computes the co-leaf rate of the
- * held-out pairs (knng_coleaf_rate, division 0) for the plain division on X
- * (p->split in R^d) and for the learned one on Z (random projection in
- * R^KNNG_MLP_EMB), and sets *use_learned to 1 only if the learned rate is
- * strictly higher.  Rates are written to the host; waits for the stream.
- * Workspace: knng_workspace_bytes(p, KNNG_OP_COLEAF).                      */
+ * held-out pairs (knng_coleaf_rate, division 0) for plain random division
+ * of X (random projection in R^d) and for the learned division (p->split
+ * applied to the embedding Z in R^KNNG_MLP_EMB), and sets *use_learned to
+ * 1 only if the learned rate is strictly higher.  Rates are written to the
+ * host; waits for the stream.  Workspace: knng_workspace_bytes(p,
+ * KNNG_OP_COLEAF).                                                          */
 int knng_learned_choice(const knng_params* p, const float* X, const float* Z, const uint32_t* pairs, int64_t n_pairs,
                         int32_t* use_learned, double* rate_plain, double* rate_learned, void* ws, size_t ws_bytes,
                         void* stream);

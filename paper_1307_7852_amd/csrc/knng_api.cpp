@@ -822,11 +822,11 @@ int knng_learned_choice(const knng_params* p, const float* X, const float* Z, co
   if (st) return st;
   if (!use_learned || !rate_plain || !rate_learned) return fail(KNNG_EINVAL, "null output pointer");
   if (p->d < KNNG_MLP_EMB) return fail(KNNG_EINVAL, "d=%d below the embedding width %d", p->d, KNNG_MLP_EMB);
-  st = knng_coleaf_rate(p, 0, X, p->d, pairs, n_pairs, rate_plain, ws, ws_bytes, stream);
+  knng_params pr = *p;
+  pr.split = KNNG_SPLIT_RP;
+  st = knng_coleaf_rate(&pr, 0, X, p->d, pairs, n_pairs, rate_plain, ws, ws_bytes, stream);
   if (st) return st;
-  knng_params pl = *p;
-  pl.split = KNNG_SPLIT_RP;
-  st = knng_coleaf_rate(&pl, 0, Z, KNNG_MLP_EMB, pairs, n_pairs, rate_learned, ws, ws_bytes, stream);
+  st = knng_coleaf_rate(p, 0, Z, KNNG_MLP_EMB, pairs, n_pairs, rate_learned, ws, ws_bytes, stream);
   if (st) return st;
   *use_learned = *rate_learned > *rate_plain ? 1 : 0;
   return KNNG_OK;

@@ -183,7 +183,10 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     S.max_n = 0u;
   }
   __syncthreads();
-  // ---- BF16: leaf mean, coalesced (threads over features x row groups)
+  // ---- BF16: leaf mean, coalesced (threads over features x row groups).
+  // A leaf whose values are all integers of magnitude <= 256 is BF16-exact
+  // as it stands: then it is not centred (centring would make it inexact),
+  // and with norms <= 2^22 its BF16 Gram with FP32 accumulation is exact.
   if constexpr (BF16) {
     float* part = reinterpret_cast<float*>(&S.tile[0]);   // >= THREADS floats, free until staging
     const int dd = d < C::THREADS ? d : C::THREADS;
@@ -191,8 +194,14 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     for (int jb = 0; jb < d; jb += dd) {
       const int jl = tid % dd, g = tid / dd, j = jb + jl;
       float acc = 0.f;
+      bool ex = true;
       if (g < G && j < d)
-        for (int i = g; i < m; i += G) acc += a.X[(size_t)S.ids[i] * d + j];
+        for (int i = g; i < m; i += G) {
+          const float v = a.X[(size_t)S.ids[i] * d + j];
+          acc += v;
+          ex = ex && v == rintf(v) && fabsf(v) <= 256.f;
+        }
+      if (!ex) S.flag = 0;
       if (g < G) part[g * dd + jl] = acc;
       __syncthreads();
       if (tid < dd && jb + tid < d) {
@@ -200,6 +209,10 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
         for (int gg = 0; gg < G; ++gg) s += part[gg * dd + tid];
         S.mu[jb + tid] = s / (float)m;
       }
+      __syncthreads();
+    }
+    if (S.flag) {   // uniform: every thread reads the flag after the last barrier
+      for (int j = tid; j < d; j += C::THREADS) S.mu[j] = 0.f;
       __syncthreads();
     }
   }
@@ -267,7 +280,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
           S.nrm[cp] = tot;
           if (kci == nchunk - 1 && cp < m) {
             atomicMax(&S.max_n, __float_as_uint(tot));
-            if (!BF16 && tot > 4194304.0f) S.flag = 0;   // 2^22: partial Gram sums stay exact
+            if (tot > 4194304.0f) S.flag = 0;   // 2^22: partial Gram sums stay exact
           }
         }
       }
@@ -448,7 +461,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     }
     wave_bitonic<R, KP, uint64_t>(kv, lane);
     const float max_n = __uint_as_float(S.max_n);
-    const bool exact_gram = !BF16 && S.flag;
+    const bool exact_gram = S.flag;
     // write rows, check the certificate on slot k-1
 #pragma unroll
     for (int r = 0; r < R; ++r) {

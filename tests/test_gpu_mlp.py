@@ -228,7 +228,7 @@ def test_build_split_on_given_embedding(dev):
 def test_training_gains_over_random_division(dev):
     """Train on a graph the method built, then on held-out points from the
     same generator compare the single-tree co-leaf rate of exact neighbour
-    pairs: learned division (random projection of the embedding) against
+    pairs: learned division (principal direction of the embedding) against
     plain random projection.  Lemma 1 turns a higher co-leaf rate into a
     higher chance that T trees put a neighbour pair in one leaf."""
     d, n = 128, 20000
@@ -246,7 +246,7 @@ def test_training_gains_over_random_division(dev):
     pairs = np.stack([np.repeat(q, 10), eids.reshape(-1)], 1)
     Xte = _tensor(Xte_np, dev)
     Z = part.embed(Xte)
-    kpt = K.Params(n=n, d=d, k=10, T=1, leaf_max=256, seed=41)
+    kpt = K.Params(n=n, d=d, k=10, T=1, leaf_max=256, seed=41, split=K.SPLIT_PCA)
     ws = K.alloc_workspace(kpt, K.OP_COLEAF, dev)
     use, r_plain, r_learned = K.learned_choice(kpt, Xte, Z, _tensor(pairs, dev, torch.int32), ws)
     say(f"co-leaf rate: random projection {r_plain:.3f}, learned {r_learned:.3f}")
