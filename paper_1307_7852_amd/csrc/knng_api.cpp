@@ -888,7 +888,7 @@ int knng_mlp_forward(int32_t d, int32_t precision, float scale, const float* par
 }
 
 namespace {
-constexpr int64_t MLP_CHUNK_ROWS = 512;
+constexpr int64_t MLP_CHUNK_ROWS = 64;   // 16384 rows -> 256 workgroups, one per CU
 // Z | Hs | dZ | dA | loss parts | chunk partials | grads | rows | loss
 struct MlpLayout { size_t Z, Hs, dZ, dA, lpart, part, grads, rows, loss, total; int64_t R, chunks, P; int nlp; };
 MlpLayout mlp_layout(int d, int n_pos, int n_neg) {
