@@ -155,6 +155,9 @@ def main():
     ap.add_argument("--queries", type=int, default=1000, help="recall sample size")
     ap.add_argument("--cpu-sample", type=int, default=20000, help="points for the CPU oracle leg (0: skip)")
     ap.add_argument("--train-steps", type=int, default=1500, help="Adam steps for the learned division")
+    ap.add_argument("--autotune", action="store_true", help="autotune the leaf tiles before timing")
+    ap.add_argument("--tune-cache", default=None, help="JSON file of leaf tile choices (read if present, else written)")
+    ap.add_argument("--graph-steps", type=int, default=3, help="HIP-graph replays timed after the eager steps (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a plain copy kernel of known size, for scaling "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -214,6 +217,20 @@ def main():
     dist = torch.empty((w.n, w.k), dtype=torch.float32, device=dev)
     log(f"workspace {ws.numel() / 2**30:.2f} GiB")
 
+    tiles = None
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        tiles = K.load_leaf_tuning(args.tune_cache)
+        log(f"leaf tiles from {args.tune_cache}: {tiles}")
+    elif args.autotune:
+        # tree shapes do not depend on the data, so a learned build's leaves
+        # have the shapes of X's own divisions: tune on X
+        tstream = torch.cuda.Stream()
+        with torch.cuda.stream(tstream):
+            tiles = [K.leaf_tune(kp, X_t, ws)]
+        log(f"autotuned leaf tiles: {tiles}")
+        if args.tune_cache:
+            K.save_leaf_tuning(args.tune_cache, tiles)
+
     def step(timed):
         if learned:
             e0 = torch.cuda.Event(enable_timing=True)
@@ -240,6 +257,27 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = 1000.0 * wall / args.steps
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step")
+    graph_ms = None
+    if args.graph_steps > 0:
+        gstream = torch.cuda.Stream()
+        ids_g = torch.empty_like(ids)
+        dist_g = torch.empty_like(dist)
+        ws_g = K.alloc_workspace(kp, K.OP_BUILD, dev)
+        with torch.cuda.stream(gstream):
+            if learned:
+                K.mlp_forward(w.d, part.precision, part.scale, part.params, X_t, Z)
+            g = K.BuildGraph(kp, X_t, Z if learned else X_t, ids_g, dist_g, ws_g)
+            g.launch()
+        gstream.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(gstream):
+            for i in range(args.graph_steps):
+                g.launch()
+        gstream.synchronize()
+        graph_ms = 1000.0 * (time.perf_counter() - t0) / args.graph_steps
+        g.close()
+        del ws_g
+        log(f"graph replays: {graph_ms:.2f} ms/step (build only{', embedding excluded' if learned else ''})")
     diag = K.read_diag(kp, ws, K.OP_BUILD)
 
     # stage totals (ms per step, averaged)
@@ -303,6 +341,10 @@ def main():
     }
     if train_info is not None:
         out["partitioner"] = {"training": train_info, "fallback_rule": choice}
+    if graph_ms is not None:
+        out["graph_ms_per_step"] = round(graph_ms, 3)
+    if tiles is not None:
+        out["leaf_tiles"] = tiles
     if args.cpu_sample > 0:
         log(f"cpu baseline on {args.cpu_sample} points")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)

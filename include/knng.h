@@ -285,6 +285,47 @@ int knng_mlp_train(int32_t d, int32_t precision, float scale, float* params, flo
                    int32_t n_pos, int32_t n_neg, float lam, float margin, float lr, float* losses, void* ws,
                    size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Leaf tile configuration (the batched leaf launch of added form (2)).
+ * The leaf kernel runs one workgroup per leaf with `waves` waves (4 or 8)
+ * and stages `kc` features of 32 candidates per tile (32, 64 or 128).  A
+ * configuration applies to one shape class: input dimension d, precision,
+ * list length class kp (k + rerank_m rounded up to 16, 32 or 64) and leaf
+ * bucket (the largest leaf of the launch rounded up to a power of two in
+ * [64, 2048]).  Classes without one use the defaults (8 waves, 4 for
+ * kp = 64; kc = 32, 64 or 128 as d <= 32, <= 64, larger).  The table is
+ * process-wide and shared by all threads.
+ * ------------------------------------------------------------------------- */
+
+/* Sets (waves, kc) for a shape class; waves = kc = 0 restores the default. */
+int knng_leaf_set_config(int32_t d, int32_t precision, int32_t kp, int32_t leaf_bucket, int32_t waves, int32_t kc);
+
+/* Autotuner: runs the T divisions of p on X once, then times the batched
+ * leaf launch over those leaves for every configuration that fits (waves
+ * in {8, 4}; kc from {64, 128} for d > 64, {32, 64} for 32 < d <= 64, 32
+ * otherwise; one warm-up and the mean of 3 timed launches each), stores
+ * the fastest for p's shape class and returns it with its time and the
+ * leaf bucket.  Needs a non-null stream; waits for it.  Workspace:
+ * knng_workspace_bytes(p, KNNG_OP_BUILD).                                  */
+int knng_leaf_tune(const knng_params* p, const float* X, void* ws, size_t ws_bytes, void* stream, int32_t* waves_out,
+                   int32_t* kc_out, float* ms_out, int32_t* leaf_bucket_out);
+
+/* HIP-graph form of knng_build_split (S = X, ds = p->d for knng_build):
+ * runs the build once eagerly (which uploads the tree plans into ws and
+ * performs every lazy kernel set-up), then captures the same launch
+ * sequence (kernels and device-to-device copies only) on `stream` (non-null)
+ * and instantiates it.  *graph receives an opaque handle.  X, S, ids, dist
+ * and ws are baked into the graph: they must stay allocated, and ws must not
+ * be used by another call, until knng_graph_destroy.                       */
+int knng_graph_create(const knng_params* p, const float* X, const float* S, int32_t ds, uint32_t* ids, float* dist,
+                      void* ws, size_t ws_bytes, void* stream, void** graph);
+
+/* Enqueues one replay of the captured build on `stream`.                  */
+int knng_graph_launch(void* graph, void* stream);
+
+/* Frees a graph (NULL is accepted).                                        */
+int knng_graph_destroy(void* graph);
+
 /* Copies the diagnostics of the last call that used workspace `ws` to the
  * host; waits for `stream`.                                                */
 int knng_read_diag(const knng_params* p, const void* ws, int op, knng_diag* out, void* stream);

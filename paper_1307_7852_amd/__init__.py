@@ -4,15 +4,16 @@ ABI of include/knng.h.  This package is the thin Python side: the ctypes
 binding plus torch helpers for device buffers."""
 from . import _lib
 from ._lib import (BF16, FP32, MLP_EMB, MLP_HIDDEN, NONE, OP_BUILD, OP_COLEAF, OP_DIVIDE, OP_LEAF, OP_MERGE,
-                   OP_PROPAGATE, SPLIT_PCA, SPLIT_RP, KnngError, Params, build, build_split, build_timed, coleaf_rate,
-                   divide, leaf_knn, learned_choice, merge, mlp_adam, mlp_forward, mlp_grad, mlp_init, mlp_param_count,
+                   OP_PROPAGATE, SPLIT_PCA, SPLIT_RP, BuildGraph, KnngError, Params, build, build_split, build_timed, coleaf_rate,
+                   divide, leaf_knn, leaf_set_config, leaf_tune, learned_choice, merge, mlp_adam, mlp_forward, mlp_grad, mlp_init, mlp_param_count,
                    mlp_sample_pairs, mlp_train, mlp_workspace_bytes, propagate, read_diag, tree_shape, workspace_bytes)
 
 __all__ = ["Params", "KnngError", "build", "build_split", "build_timed", "coleaf_rate", "learned_choice", "divide", "leaf_knn", "merge",
            "propagate", "read_diag", "tree_shape", "workspace_bytes", "alloc_workspace", "knn_graph", "NONE", "FP32",
            "BF16", "SPLIT_RP", "SPLIT_PCA", "OP_DIVIDE", "OP_LEAF", "OP_MERGE", "OP_PROPAGATE", "OP_BUILD", "OP_COLEAF",
            "MLP_HIDDEN", "MLP_EMB", "mlp_param_count", "mlp_init", "mlp_forward", "mlp_workspace_bytes", "mlp_grad",
-           "mlp_adam", "mlp_sample_pairs", "mlp_train", "Partitioner"]
+           "mlp_adam", "mlp_sample_pairs", "mlp_train", "Partitioner", "BuildGraph", "leaf_tune",
+           "leaf_set_config", "save_leaf_tuning", "load_leaf_tuning"]
 
 
 def alloc_workspace(p: Params, op: int, device="cuda"):
@@ -63,3 +64,20 @@ class Partitioner:
         Z = torch.empty((X.shape[0], MLP_EMB), dtype=torch.float32, device=X.device)
         mlp_forward(self.d, self.precision, self.scale, self.params, X, Z)
         return Z
+
+
+def save_leaf_tuning(path: str, choices: list):
+    """Writes autotuned leaf configurations (dicts from leaf_tune) as JSON."""
+    import json
+    with open(path, "w") as f:
+        json.dump(choices, f, indent=1)
+
+
+def load_leaf_tuning(path: str) -> list:
+    """Installs the configurations of a JSON file written by save_leaf_tuning."""
+    import json
+    with open(path) as f:
+        choices = json.load(f)
+    for c in choices:
+        leaf_set_config(c["d"], c["precision"], c["kp"], c["leaf_bucket"], c["waves"], c["kc"])
+    return choices

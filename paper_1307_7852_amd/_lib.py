@@ -98,6 +98,12 @@ def _load():
         "knng_coleaf_rate": (i32, [P, i32, vp, i32, vp, i64, ctypes.POINTER(ctypes.c_double), vp, sz, vp]),
         "knng_learned_choice": (i32, [P, vp, vp, vp, i64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double), vp, sz, vp]),
+        "knng_leaf_set_config": (i32, [i32, i32, i32, i32, i32, i32]),
+        "knng_leaf_tune": (i32, [P, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)]),
+        "knng_graph_create": (i32, [P, vp, vp, i32, vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_void_p)]),
+        "knng_graph_launch": (i32, [vp, vp]),
+        "knng_graph_destroy": (i32, [vp]),
         "knng_mlp_param_count": (i64, [i32]),
         "knng_mlp_init": (i32, [i32, u64, vp, vp]),
         "knng_mlp_forward": (i32, [i32, i32, f32, vp, vp, i64, vp, vp]),
@@ -119,7 +125,8 @@ _lib = _load()
 EXPORTS = ["knng_status_str", "knng_last_error", "knng_workspace_bytes", "knng_tree_shape", "knng_divide",
            "knng_leaf_knn", "knng_merge", "knng_propagate", "knng_build", "knng_read_diag", "knng_build_timed",
            "knng_build_split", "knng_coleaf_rate", "knng_learned_choice", "knng_mlp_param_count", "knng_mlp_init", "knng_mlp_forward",
-           "knng_mlp_workspace_bytes", "knng_mlp_grad", "knng_mlp_adam", "knng_mlp_sample_pairs", "knng_mlp_train"]
+           "knng_mlp_workspace_bytes", "knng_mlp_grad", "knng_mlp_adam", "knng_mlp_sample_pairs", "knng_mlp_train",
+           "knng_leaf_set_config", "knng_leaf_tune", "knng_graph_create", "knng_graph_launch", "knng_graph_destroy"]
 
 
 def _status_name(s: int) -> str:
@@ -235,6 +242,48 @@ def learned_choice(p: Params, X, Z, pairs, ws, stream=None):
                                     ctypes.byref(use), ctypes.byref(rp), ctypes.byref(rl), _ptr(ws),
                                     ws.numel() * ws.element_size(), _stream(stream)))
     return bool(use.value), rp.value, rl.value
+
+
+def leaf_set_config(d: int, precision: int, kp: int, leaf_bucket: int, waves: int, kc: int):
+    _check(_lib.knng_leaf_set_config(d, precision, kp, leaf_bucket, waves, kc))
+
+
+def leaf_tune(p: Params, X, ws, stream=None) -> dict:
+    """Autotunes the leaf tiles for p's shape class; returns the choice."""
+    cp = p.c()
+    wv, kc, lb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    ms = ctypes.c_float()
+    _check(_lib.knng_leaf_tune(ctypes.byref(cp), _ptr(X), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream),
+                               ctypes.byref(wv), ctypes.byref(kc), ctypes.byref(ms), ctypes.byref(lb)))
+    kp = p.k + p.rerank_m
+    return {"d": p.d, "precision": p.precision, "kp": 16 if kp <= 16 else 32 if kp <= 32 else 64,
+            "leaf_bucket": lb.value, "waves": wv.value, "kc": kc.value, "ms": ms.value}
+
+
+class BuildGraph:
+    """A captured build (knng_graph_create); replay with launch()."""
+
+    def __init__(self, p: Params, X, S, ids, dist, ws, stream=None):
+        cp = p.c()
+        h = ctypes.c_void_p()
+        self._keep = (X, S, ids, dist, ws)   # the graph holds their addresses
+        _check(_lib.knng_graph_create(ctypes.byref(cp), _ptr(X), _ptr(S), int(S.shape[1]), _ptr(ids), _ptr(dist),
+                                      _ptr(ws), ws.numel() * ws.element_size(), _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(_lib.knng_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            _check(_lib.knng_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mlp_param_count(d: int) -> int:

@@ -386,6 +386,37 @@ int upload_blob(const Batch& B, char* dst, hipStream_t s) {
   return KNNG_OK;
 }
 
+// ------------------------------------------------------------------ leaf tile configuration
+// Chosen per shape class (d, precision, list length kp, leaf-size bucket):
+// workgroup waves and the feature chunk staged per tile.  Unset classes use
+// the kernel's defaults.
+struct TuneKey {
+  int d, precision, kp, bucket;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(d, precision, kp, bucket) < std::tie(o.d, o.precision, o.kp, o.bucket);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;
+
+int kp_class(const knng_params& p) {
+  const int kp = p.k + p.rerank_m;
+  return kp <= 16 ? 16 : kp <= 32 ? 32 : 64;
+}
+int leaf_bucket(int64_t max_leaf) {
+  int b = 64;
+  while (b < max_leaf && b < KNNG_MAX_LEAF) b *= 2;
+  return b;
+}
+void apply_tune(const knng_params& p, int64_t max_leaf, LeafArgs& a) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(TuneKey{p.d, p.precision, kp_class(p), leaf_bucket(max_leaf)});
+  if (it != g_tune.end()) {
+    a.waves = it->second.first;
+    a.kc = it->second.second;
+  }
+}
+
 int leaf_single(const knng_params& p, const float* X, const uint32_t* perm, const int64_t* leaf_off, int64_t n_leaves,
                 uint32_t* ids, float* dist, char* scratch, DiagDev* diag, hipStream_t s) {
   LeafLayout L = leaf_layout(p, 1);
@@ -396,12 +427,14 @@ int leaf_single(const knng_params& p, const float* X, const uint32_t* perm, cons
   a.fallback = (uint32_t*)(scratch + L.fallback);
   a.fallback_cap = (uint64_t)p.n;
   a.diag = diag;
+  apply_tune(p, 2 * (int64_t)p.leaf_max, a);
   HIP_TRY(launch_leaf(a, s));
   return KNNG_OK;
 }
 
 int leaf_batched(const knng_params& p, const Batch& B, const char* blob_dev, const float* X, const uint32_t* perms,
-                 uint32_t* ids, float* dist, char* scratch, DiagDev* diag, hipStream_t s) {
+                 uint32_t* ids, float* dist, char* scratch, DiagDev* diag, hipStream_t s, int waves = -1, int kc = -1,
+                 bool prepare_only = false) {
   LeafLayout L = leaf_layout(p, B.slots);
   LeafArgs a{};
   a.X = X; a.n = p.n; a.d = p.d; a.k = p.k; a.kp = p.k + p.rerank_m; a.precision = p.precision;
@@ -414,7 +447,17 @@ int leaf_batched(const knng_params& p, const Batch& B, const char* blob_dev, con
   a.fallback = (uint32_t*)(scratch + L.fallback);
   a.fallback_cap = (uint64_t)B.slots * p.n;
   a.diag = diag;
-  HIP_TRY(launch_leaf(a, s));
+  if (waves < 0) {
+    apply_tune(p, B.work.empty() ? 1 : (int64_t)B.work[0].m, a);   // the work list is largest first
+  } else {
+    a.waves = waves;
+    a.kc = kc;
+  }
+  a.prepare_only = prepare_only;
+  hipError_t e = launch_leaf(a, s);
+  if (e == hipErrorInvalidConfiguration || e == hipErrorInvalidValue)
+    return fail(KNNG_EUNSUPPORTED, "leaf tile configuration (waves %d, kc %d) does not fit", a.waves, a.kc);
+  HIP_TRY(e);
   return KNNG_OK;
 }
 
@@ -694,7 +737,7 @@ int knng_propagate(const knng_params* p, const float* X, uint32_t* ids, float* d
 // division 0's leaf order (neighbouring points share candidates, so their
 // rows stay in cache).
 static int build_impl(const knng_params* p, const float* X, const float* S, int ds, uint32_t* ids, float* dist,
-                      void* ws, size_t ws_bytes, void* stream, std::vector<hipEvent_t>* ev) {
+                      void* ws, size_t ws_bytes, void* stream, std::vector<hipEvent_t>* ev, bool upload = true) {
   int st = validate(p);
   if (st) return st;
   if (!X || !S || !ids || !dist || !ws) return fail(KNNG_EINVAL, "null array argument");
@@ -713,8 +756,10 @@ static int build_impl(const knng_params* p, const float* X, const float* S, int 
   if (!B) return st;
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
-  st = upload_blob(*B, w + BL.blob, s);
-  if (st) return st;
+  if (upload) {
+    st = upload_blob(*B, w + BL.blob, s);
+    if (st) return st;
+  }
   DiagDev* diag = (DiagDev*)(w + BL.diag);
   HIP_TRY(zero_diag(diag, s));
   auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord((*ev)[i], s) : hipSuccess; };
@@ -829,6 +874,151 @@ int knng_learned_choice(const knng_params* p, const float* X, const float* Z, co
   st = knng_coleaf_rate(p, 0, Z, KNNG_MLP_EMB, pairs, n_pairs, rate_learned, ws, ws_bytes, stream);
   if (st) return st;
   *use_learned = *rate_learned > *rate_plain ? 1 : 0;
+  return KNNG_OK;
+}
+
+int knng_leaf_set_config(int32_t d, int32_t precision, int32_t kp, int32_t leaf_bucket, int32_t waves, int32_t kc) {
+  if (d < 4 || d > 4096 || (precision != KNNG_FP32 && precision != KNNG_BF16) || (kp != 16 && kp != 32 && kp != 64))
+    return fail(KNNG_EINVAL, "invalid shape class (d %d, precision %d, kp %d)", d, precision, kp);
+  if (leaf_bucket < 64 || leaf_bucket > KNNG_MAX_LEAF || (leaf_bucket & (leaf_bucket - 1)))
+    return fail(KNNG_EINVAL, "leaf_bucket=%d must be a power of two in [64, %d]", leaf_bucket, KNNG_MAX_LEAF);
+  if (!((waves == 0 && kc == 0) || ((waves == 4 || waves == 8) && (kc == 32 || kc == 64 || kc == 128))))
+    return fail(KNNG_EINVAL, "need waves in {4, 8} and kc in {32, 64, 128}, or both 0 for the default");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  TuneKey key{d, precision, kp, leaf_bucket};
+  if (waves == 0) g_tune.erase(key);
+  else g_tune[key] = {waves, kc};
+  return KNNG_OK;
+}
+
+int knng_leaf_tune(const knng_params* p, const float* X, void* ws, size_t ws_bytes, void* stream, int32_t* waves_out,
+                   int32_t* kc_out, float* ms_out, int32_t* leaf_bucket_out) {
+  int st = validate(p);
+  if (st) return st;
+  if (!X || !ws || !waves_out || !kc_out || !ms_out || !leaf_bucket_out) return fail(KNNG_EINVAL, "null argument");
+  if (!aligned16(X)) return fail(KNNG_EINVAL, "X must be 16-byte aligned");
+  if (((uintptr_t)ws & 255) != 0) return fail(KNNG_EINVAL, "ws must be 256-byte aligned");
+  if (!stream) return fail(KNNG_EINVAL, "tuning needs a non-null stream");
+  BuildLayout BL;
+  st = build_layout(*p, BL);
+  if (st) return st;
+  if (ws_bytes < BL.total) return fail(KNNG_ENOMEM, "tuning needs %zu workspace bytes, got %zu", BL.total, ws_bytes);
+  BatchPtr B = get_batch(*p, all_divisions(*p), &st);
+  if (!B) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  st = upload_blob(*B, w + BL.blob, s);
+  if (st) return st;
+  DiagDev* diag = (DiagDev*)(w + BL.diag);
+  uint32_t* permA = (uint32_t*)(w + BL.permA);
+  uint32_t* permB = (uint32_t*)(w + BL.permB);
+  char* sh = w + BL.shared;
+  HIP_TRY(zero_diag(diag, s));
+  st = divide_core(*p, *B, w + BL.blob, X, nullptr, nullptr, permA, permB, sh, s);
+  if (st) return st;
+  const uint32_t* perms = (B->depth % 2 == 0) ? permA : permB;
+  uint32_t* lids = (uint32_t*)(w + BL.lists_ids);
+  float* ldist = (float*)(w + BL.lists_dist);
+  std::vector<int> kcs;
+  if (p->d <= 32) kcs = {32};
+  else if (p->d <= 64) kcs = {32, 64};
+  else kcs = {64, 128};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(KNNG_EHIP, "hipEventCreate failed");
+  }
+  float best = 1e30f;
+  int bw = 0, bk = 0;
+  st = KNNG_OK;
+  for (int wv : {8, 4}) {
+    for (int kc : kcs) {
+      int r = leaf_batched(*p, *B, w + BL.blob, X, perms, lids, ldist, sh, diag, s, wv, kc);   // warm-up
+      if (r == KNNG_EUNSUPPORTED) continue;
+      if (r) { st = r; break; }
+      float tot = 0.f;
+      for (int rep = 0; rep < 3 && st == KNNG_OK; ++rep) {
+        float ms = 0.f;
+        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(KNNG_EHIP, "hipEventRecord failed"); break; }
+        r = leaf_batched(*p, *B, w + BL.blob, X, perms, lids, ldist, sh, diag, s, wv, kc);
+        if (r) { st = r; break; }
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = fail(KNNG_EHIP, "event timing failed"); break; }
+        tot += ms;
+      }
+      if (st) break;
+      if (tot / 3 < best) { best = tot / 3; bw = wv; bk = kc; }
+    }
+    if (st) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  if (bw == 0) return fail(KNNG_EUNSUPPORTED, "no leaf tile configuration fits");
+  const int bucket = leaf_bucket(B->work.empty() ? 1 : (int64_t)B->work[0].m);
+  st = knng_leaf_set_config(p->d, p->precision, kp_class(*p), bucket, bw, bk);
+  if (st) return st;
+  *waves_out = bw;
+  *kc_out = bk;
+  *ms_out = best;
+  *leaf_bucket_out = bucket;
+  return KNNG_OK;
+}
+
+struct KnngGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int knng_graph_create(const knng_params* p, const float* X, const float* S, int32_t ds, uint32_t* ids, float* dist,
+                      void* ws, size_t ws_bytes, void* stream, void** graph) {
+  if (!graph) return fail(KNNG_EINVAL, "null graph output");
+  *graph = nullptr;
+  if (!stream) return fail(KNNG_EINVAL, "graph capture needs a non-null stream");
+  hipStream_t s = (hipStream_t)stream;
+  // one eager build: uploads the plan into ws and performs every lazy
+  // kernel set-up, so the captured sequence holds launches and device copies only
+  int st = build_impl(p, X, S, ds, ids, dist, ws, ws_bytes, stream, nullptr, true);
+  if (st) return st;
+  HIP_TRY(hipStreamSynchronize(s));
+  KnngGraph* G = new KnngGraph();
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    delete G;
+    return fail(KNNG_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  st = build_impl(p, X, S, ds, ids, dist, ws, ws_bytes, stream, nullptr, false);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(s, &g);
+  if (st || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    delete G;
+    return st ? st : fail(KNNG_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  }
+  G->graph = g;
+  e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    delete G;
+    return fail(KNNG_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  *graph = G;
+  return KNNG_OK;
+}
+
+int knng_graph_launch(void* graph, void* stream) {
+  if (!graph) return fail(KNNG_EINVAL, "null graph");
+  HIP_TRY(hipGraphLaunch(((KnngGraph*)graph)->exec, (hipStream_t)stream));
+  return KNNG_OK;
+}
+
+int knng_graph_destroy(void* graph) {
+  if (!graph) return KNNG_OK;
+  KnngGraph* G = (KnngGraph*)graph;
+  if (G->exec) (void)hipGraphExecDestroy(G->exec);
+  if (G->graph) (void)hipGraphDestroy(G->graph);
+  delete G;
   return KNNG_OK;
 }
 

@@ -138,6 +138,9 @@ struct LeafArgs {
   uint32_t* fallback;        // (leaf or work index, position) pairs, capacity fallback_cap
   uint64_t fallback_cap;
   DiagDev* diag;
+  int waves;                 // workgroup waves (4 or 8; 0: the default for kp)
+  int kc;                    // feature chunk staged per tile (32, 64, 128; 0: chosen from d)
+  bool prepare_only;         // set kernel attributes and occupancy, launch nothing
 };
 hipError_t launch_leaf(const LeafArgs& a, hipStream_t s);
 

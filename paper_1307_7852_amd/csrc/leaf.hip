@@ -1,6 +1,7 @@
 // Exact k-NN inside every leaf subset (Section 3.1's brute-force subgraph).
 //
-// One workgroup (8 waves; 4 for k + rerank_m > 32) per leaf.  The leaf's
+// One workgroup per leaf: 8 waves by default (4 for k + rerank_m > 32);
+// the wave count and the K-chunk width are tunable per shape.  The leaf's
 // members stream through LDS in tiles of 32 candidates x KC features
 // (double-buffered, staged once for all waves; rows padded so operand reads
 // are bank-conflict free).  Each wave owns 32 queries whose fragments sit in
@@ -43,9 +44,9 @@ constexpr uint32_t KEY_VALID = 0x7F000000u;    // keys at or above this are padd
 constexpr float PAD_NORM = 3e38f;              // norm given to padding rows (keys land above KEY_VALID)
 constexpr float KEY_FLOOR = 0x1p-100f;         // keeps every key a normal float
 
-template <int KP>
+template <int KP, int W>
 struct Cfg {
-  static constexpr int WAVES = (KP <= 32) ? 8 : 4;
+  static constexpr int WAVES = W;
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int QPB = QPW * WAVES;   // queries per pass
   static constexpr int LS = KP + 1;         // list stride per query in LDS
@@ -109,9 +110,9 @@ struct TileT {
   E v[TILE * STRIDE];
 };
 
-template <int KC, int KP, bool BF16>
+template <int KC, int KP, bool BF16, int W>
 struct LeafShared {
-  using C = Cfg<KP>;
+  using C = Cfg<KP, W>;
   uint32_t ids[KNNG_MAX_LEAF];
   float nrm[KNNG_MAX_LEAF];                 // member norms (BF16: of the rounded centred rows)
   TileT<KC, BF16> tile[2];
@@ -154,11 +155,11 @@ struct QFrag {
 
 // One leaf: members perm[off .. off+m), rows written to ids/dist (already
 // offset to the leaf's division).  `key` names the leaf in the fallback list.
-template <int KC, int KP, bool BF16>
-__device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, BF16>& S, const uint32_t* __restrict__ perm,
+template <int KC, int KP, bool BF16, int W>
+__device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, BF16, W>& S, const uint32_t* __restrict__ perm,
                                           uint32_t* __restrict__ ids_out, float* __restrict__ dist_out, int64_t off,
                                           int m, uint32_t key) {
-  using C = Cfg<KP>;
+  using C = Cfg<KP, W>;
   using Tile = TileT<KC, BF16>;
   constexpr int LS = C::LS;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, h = lane >> 5, r32 = lane & 31;
@@ -512,10 +513,10 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
 // Single-division mode: one workgroup per leaf.  Batched mode: a persistent
 // grid; each workgroup takes the next leaf from the work list (largest
 // first) until the list is exhausted, so every workgroup reaches the exit.
-template <int KC, int KP, bool BF16>
-__global__ __launch_bounds__(Cfg<KP>::THREADS) void k_leaf(LeafArgs a) {
+template <int KC, int KP, bool BF16, int W>
+__global__ __launch_bounds__((Cfg<KP, W>::THREADS)) void k_leaf(LeafArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  using Sh = LeafShared<KC, KP, BF16>;
+  using Sh = LeafShared<KC, KP, BF16, W>;
   Sh& S = *reinterpret_cast<Sh*>(smem_raw);
   __shared__ uint32_t next;
   // single-division mode runs one pass of the loop for leaf blockIdx.x
@@ -547,7 +548,7 @@ __global__ __launch_bounds__(Cfg<KP>::THREADS) void k_leaf(LeafArgs a) {
       off = a.leaf_off[idx];
       m = (int)(a.leaf_off[idx + 1] - off);
     }
-    leaf_body<KC, KP, BF16>(a, S, perm, ids_out, dist_out, off, m, idx);
+    leaf_body<KC, KP, BF16, W>(a, S, perm, ids_out, dist_out, off, m, idx);
     __syncthreads();
   }
 }
@@ -630,52 +631,68 @@ __global__ __launch_bounds__(256) void k_leaf_exact(LeafArgs a) {
   }
 }
 
-template <int KC, int KP, bool BF16>
+template <int KC, int KP, bool BF16, int W>
 hipError_t launch_leaf_t(const LeafArgs& a, hipStream_t s) {
-  size_t shm = sizeof(LeafShared<KC, KP, BF16>);
-  auto kern = k_leaf<KC, KP, BF16>;
-  constexpr int THREADS = Cfg<KP>::THREADS;
-  static int per_cu = 0;
-  if (per_cu == 0) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    int occ = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, THREADS, shm);
-    per_cu = (e == hipSuccess && occ > 0) ? occ : 1;
-  }
-  if (a.work) {
-    hipError_t e = launch_fill_u32(a.counter, 0u, 1, s);
-    if (e != hipSuccess) return e;
-    unsigned grid = (unsigned)std::min<uint64_t>(a.n_work, (uint64_t)a.grid * per_cu);
-    if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(THREADS), shm, s, a);
+  using Sh = LeafShared<KC, KP, BF16, W>;
+  if constexpr (sizeof(Sh) + 64 > 160 * 1024) {
+    return hipErrorInvalidConfiguration;   // this tile shape does not fit a CU's LDS
   } else {
-    hipLaunchKernelGGL(kern, dim3((unsigned)a.n_leaves), dim3(THREADS), shm, s, a);
+    size_t shm = sizeof(Sh);
+    auto kern = k_leaf<KC, KP, BF16, W>;
+    constexpr int THREADS = Cfg<KP, W>::THREADS;
+    static int per_cu = 0;
+    if (per_cu == 0) {
+      hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      if (e != hipSuccess) return e;
+      int occ = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)kern, THREADS, shm);
+      per_cu = (e == hipSuccess && occ > 0) ? occ : 1;
+    }
+    if (a.prepare_only) return hipSuccess;
+    if (a.work) {
+      hipError_t e = launch_fill_u32(a.counter, 0u, 1, s);
+      if (e != hipSuccess) return e;
+      unsigned grid = (unsigned)std::min<uint64_t>(a.n_work, (uint64_t)a.grid * per_cu);
+      if (grid == 0) return hipSuccess;
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(THREADS), shm, s, a);
+    } else {
+      hipLaunchKernelGGL(kern, dim3((unsigned)a.n_leaves), dim3(THREADS), shm, s, a);
+    }
+    return hipGetLastError();
   }
-  return hipGetLastError();
+}
+
+template <int KC, int KP, bool BF16>
+hipError_t launch_leaf_w(const LeafArgs& a, hipStream_t s) {
+  const int w = a.waves ? a.waves : (KP <= 32 ? 8 : 4);
+  if (w == 8) return launch_leaf_t<KC, KP, BF16, 8>(a, s);
+  if (w == 4) return launch_leaf_t<KC, KP, BF16, 4>(a, s);
+  return hipErrorInvalidValue;
 }
 
 template <int KC, bool BF16>
 hipError_t launch_leaf_kp(const LeafArgs& a, hipStream_t s) {
-  if (a.kp <= 16) return launch_leaf_t<KC, 16, BF16>(a, s);
-  if (a.kp <= 32) return launch_leaf_t<KC, 32, BF16>(a, s);
-  return launch_leaf_t<KC, 64, BF16>(a, s);
+  if (a.kp <= 16) return launch_leaf_w<KC, 16, BF16>(a, s);
+  if (a.kp <= 32) return launch_leaf_w<KC, 32, BF16>(a, s);
+  return launch_leaf_w<KC, 64, BF16>(a, s);
+}
+
+template <bool BF16>
+hipError_t launch_leaf_kc(const LeafArgs& a, hipStream_t s) {
+  const int kc = a.kc ? a.kc : (a.d <= 32 ? 32 : a.d <= 64 ? 64 : 128);
+  if (kc == 32) return launch_leaf_kp<32, BF16>(a, s);
+  if (kc == 64) return launch_leaf_kp<64, BF16>(a, s);
+  if (kc == 128) return launch_leaf_kp<128, BF16>(a, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 hipError_t launch_leaf(const LeafArgs& a, hipStream_t s) {
   hipError_t e;
+  if (a.prepare_only) return a.precision == KNNG_BF16 ? launch_leaf_kc<true>(a, s) : launch_leaf_kc<false>(a, s);
   if ((e = launch_fill_u32((uint32_t*)&a.diag->fallback_count, 0u, 2, s)) != hipSuccess) return e;
-  if (a.precision == KNNG_BF16) {
-    if (a.d <= 32) e = launch_leaf_kp<32, true>(a, s);
-    else if (a.d <= 64) e = launch_leaf_kp<64, true>(a, s);
-    else e = launch_leaf_kp<128, true>(a, s);
-  } else {
-    if (a.d <= 32) e = launch_leaf_kp<32, false>(a, s);
-    else if (a.d <= 64) e = launch_leaf_kp<64, false>(a, s);
-    else e = launch_leaf_kp<128, false>(a, s);
-  }
+  e = a.precision == KNNG_BF16 ? launch_leaf_kc<true>(a, s) : launch_leaf_kc<false>(a, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_leaf_exact, dim3(1024), dim3(256), 0, s, a);
   return hipGetLastError();
