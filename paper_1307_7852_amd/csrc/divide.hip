@@ -95,7 +95,28 @@ __device__ __forceinline__ float dot_seq(const float* __restrict__ x, const floa
 #pragma clang fp contract(off)
   float acc = 0.f;
   const float4* xv = (const float4*)x;
-  for (int c = 0; c < (d >> 2); ++c) {
+  const int c4 = d >> 2;
+  int c = 0;
+  // eight float4 (a 128-byte line of the row) in flight per step; the
+  // products and sums still run left to right
+  for (; c + 8 <= c4; c += 8) {
+    float4 u[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) u[k] = xv[c + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float* ak = a + 4 * (c + k);
+      float p0 = u[k].x * ak[0];
+      acc = acc + p0;
+      float p1 = u[k].y * ak[1];
+      acc = acc + p1;
+      float p2 = u[k].z * ak[2];
+      acc = acc + p2;
+      float p3 = u[k].w * ak[3];
+      acc = acc + p3;
+    }
+  }
+  for (; c < c4; ++c) {
     float4 u = xv[c];
     float p0 = u.x * a[4 * c + 0];
     acc = acc + p0;
@@ -237,15 +258,181 @@ __global__ __launch_bounds__(DIV_THREADS) void k_part_scatter(DivideLevelArgs a)
 // t = Y v (a thread per sample row; rows padded by one float so the threads'
 // column reads fall in distinct banks) and w = Y^T t (a thread per feature).
 // Otherwise the same two passes read the rows from global memory.
-template <bool SAMPLE_LDS>
+// Principal direction of one node's sample with the whole centred sample in
+// LDS (d <= PCA_LDS_DMAX).  Rows are padded to d + 4 floats, so float4
+// reads of one column by consecutive rows fall in different banks.
+// t = Y v: a thread per sample row, float4 over the columns.  w = Y^T t: a
+// thread per (column quad, slab of rows); slab partials are added in slab
+// order.  The mean is formed the same way.  The sample, start vector,
+// iteration count and sign rule are those of k_pca_dirs.
+constexpr int PCA_LDS_DMAX = 136;   // 256 (d + 4) + 2d + 256 + 1024 floats fit 150 KB
+
+__global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
+  extern __shared__ float smem[];
+  const int d = a.d;
+  const int ld = d + 4;
+  const int cw = d >> 2;                       // column quads
+  const int G = DIV_THREADS / cw;              // row slabs
+  float* Y = smem;                             // 256 x ld
+  float* v = Y + 256 * ld;                     // d
+  float* mu = v + d;                           // d
+  float* tt = mu + d;                          // 256
+  float4* part = (float4*)(tt + 256);          // G x cw
+  __shared__ uint32_t rows[256];
+  __shared__ float red[DIV_THREADS / 64];
+  __shared__ int redi[DIV_THREADS / 64];
+  const SegDesc sd = a.segs[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t m = sd.m;
+  const uint32_t s = m < 256 ? m : 256;
+  uint32_t wd = m / s;
+  if (wd < 1) wd = 1;
+  if (tid < (int)s) {
+    uint32_t pos = (uint32_t)(((uint64_t)tid * m) / s) + (uint32_t)(rand64(a.seed, TAG_SAMPLE, sd.t, sd.v, tid) % wd);
+    rows[tid] = a.perm_in[(size_t)sd.slot * (size_t)a.n + sd.off + pos];
+  }
+  for (int j = tid; j < d; j += DIV_THREADS) v[j] = rp_entry(a.seed, sd.t, sd.v, (uint32_t)j);
+  __syncthreads();
+  // raw sample -> LDS, 8 loads in flight per thread
+  {
+    const int tot = (int)s * cw;
+    for (int e0 = tid; e0 < tot; e0 += DIV_THREADS * 8) {
+      float4 buf[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int e = e0 + u * DIV_THREADS;
+        buf[u] = e < tot ? ((const float4*)(a.X + (size_t)rows[e / cw] * d))[e % cw] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int e = e0 + u * DIV_THREADS;
+        if (e < tot) *(float4*)(Y + (e / cw) * ld + 4 * (e % cw)) = buf[u];
+      }
+    }
+  }
+  __syncthreads();
+  const int q = tid % cw, g = tid / cw;
+  const uint32_t rps = (s + G - 1) / G;        // rows per slab
+  // column sums over a slab of rows, weighted by wt[i] (or 1), into part[g][q]
+  auto slab_sums = [&](const float* wt) {
+    if (g < G) {
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      const uint32_t i0 = g * rps, i1 = min(s, i0 + rps);
+      for (uint32_t i = i0; i < i1; ++i) {
+        const float4 y = *(const float4*)(Y + i * ld + 4 * q);
+        const float c = wt ? wt[i] : 1.f;
+        acc.x = __builtin_fmaf(y.x, c, acc.x);
+        acc.y = __builtin_fmaf(y.y, c, acc.y);
+        acc.z = __builtin_fmaf(y.z, c, acc.z);
+        acc.w = __builtin_fmaf(y.w, c, acc.w);
+      }
+      part[g * cw + q] = acc;
+    }
+    __syncthreads();
+  };
+  auto col_total = [&](int qq) -> float4 {
+    float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int gg = 0; gg < G; ++gg) {
+      const float4 p4 = part[gg * cw + qq];
+      r.x += p4.x; r.y += p4.y; r.z += p4.z; r.w += p4.w;
+    }
+    return r;
+  };
+  auto block_sum = [&](float x) -> float {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (lane == 0) red[wv] = x;
+    __syncthreads();
+    float r = 0.f;
+    for (int i = 0; i < DIV_THREADS / 64; ++i) r += red[i];
+    __syncthreads();
+    return r;
+  };
+  // mean and centring
+  slab_sums(nullptr);
+  if (tid < cw) {
+    const float4 t4 = col_total(tid);
+    const float is = 1.0f / (float)s;
+    mu[4 * tid + 0] = t4.x * is;
+    mu[4 * tid + 1] = t4.y * is;
+    mu[4 * tid + 2] = t4.z * is;
+    mu[4 * tid + 3] = t4.w * is;
+  }
+  __syncthreads();
+  for (int e = tid; e < (int)s * cw; e += DIV_THREADS) {
+    float4* yr = (float4*)(Y + (e / cw) * ld + 4 * (e % cw));
+    const float4 m4 = *(const float4*)(mu + 4 * (e % cw));
+    float4 y = *yr;
+    y.x -= m4.x; y.y -= m4.y; y.z -= m4.z; y.w -= m4.w;
+    *yr = y;
+  }
+  // normalise the start vector
+  float nn = 0.f;
+  for (int j = tid; j < d; j += DIV_THREADS) nn += v[j] * v[j];
+  nn = block_sum(nn);
+  {
+    const float inv = nn > 0.f ? 1.0f / sqrtf(nn) : 0.f;
+    for (int j = tid; j < d; j += DIV_THREADS) v[j] *= inv;
+  }
+  __syncthreads();
+  for (int itr = 0; itr < a.pca_iters; ++itr) {
+    if (tid < (int)s) {   // t = Y v
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      const float* yr = Y + tid * ld;
+      for (int c = 0; c < cw; ++c) {
+        const float4 y = *(const float4*)(yr + 4 * c);
+        const float4 vv = *(const float4*)(v + 4 * c);
+        acc.x = __builtin_fmaf(y.x, vv.x, acc.x);
+        acc.y = __builtin_fmaf(y.y, vv.y, acc.y);
+        acc.z = __builtin_fmaf(y.z, vv.z, acc.z);
+        acc.w = __builtin_fmaf(y.w, vv.w, acc.w);
+      }
+      tt[tid] = (acc.x + acc.y) + (acc.z + acc.w);
+    }
+    __syncthreads();
+    slab_sums(tt);   // w = Y^T t, by slabs
+    float sq = 0.f;
+    float4 w4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (tid < cw) {
+      w4 = col_total(tid);
+      sq = w4.x * w4.x + w4.y * w4.y + w4.z * w4.z + w4.w * w4.w;
+    }
+    sq = block_sum(sq);
+    if (sq > 0.f && tid < cw) {
+      const float iv = 1.0f / sqrtf(sq);
+      *(float4*)(v + 4 * tid) = make_float4(w4.x * iv, w4.y * iv, w4.z * iv, w4.w * iv);
+    }
+    __syncthreads();
+  }
+  // sign: the largest-magnitude entry positive, lowest index on ties
+  float best = -1.f;
+  int bj = 0x7FFFFFFF;
+  for (int j = tid; j < d; j += DIV_THREADS) {
+    float av = fabsf(v[j]);
+    if (av > best) { best = av; bj = j; }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    float ob = __shfl_xor(best, o);
+    int oj = __shfl_xor(bj, o);
+    if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+  }
+  if (lane == 0) { red[wv] = best; redi[wv] = bj; }
+  __syncthreads();
+  best = red[0]; bj = redi[0];
+  for (int i = 1; i < DIV_THREADS / 64; ++i)
+    if (red[i] > best || (red[i] == best && redi[i] < bj)) { best = red[i]; bj = redi[i]; }
+  const float sg = v[bj] < 0.f ? -1.f : 1.f;
+  for (int j = tid; j < d; j += DIV_THREADS) a.pca_dirs[(size_t)sd.dir_index * d + j] = sg * v[j];
+}
+
+// Principal direction for d > PCA_LDS_DMAX: the centred sample is read from
+// global memory (L2) in every iteration; same sample, start, iterations and
+// sign rule as k_pca_lds.
 __global__ __launch_bounds__(DIV_THREADS) void k_pca_dirs(DivideLevelArgs a) {
   extern __shared__ float smem[];
   const int d = a.d;
-  const int ld = d + 1;           // padded row stride in LDS
   float* mu = smem;               // d
   float* v = mu + d;              // d
   float* tt = v + d;              // 256
-  float* Y = tt + 256;            // 256 x (d + 1) when SAMPLE_LDS
   __shared__ uint32_t rows[256];
   __shared__ float red[DIV_THREADS / 64];
   __shared__ int redi[DIV_THREADS / 64];
@@ -262,46 +449,13 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_dirs(DivideLevelArgs a) {
   }
   for (int j = threadIdx.x; j < d; j += DIV_THREADS) v[j] = rp_entry(a.seed, sd.t, sd.v, (uint32_t)j);
   __syncthreads();
-  if constexpr (SAMPLE_LDS) {
-    // raw sample -> LDS: element e = (row, float4 column), 8 loads in flight per thread
-    const int c4 = d >> 2, tot = (int)s * c4;
-    for (int e0 = threadIdx.x; e0 < tot; e0 += DIV_THREADS * 8) {
-      float4 buf[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        int e = e0 + u * DIV_THREADS;
-        buf[u] = e < tot ? ((const float4*)(a.X + (size_t)rows[e / c4] * d))[e % c4] : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        int e = e0 + u * DIV_THREADS;
-        if (e < tot) {
-          float* yr = Y + (e / c4) * ld + 4 * (e % c4);
-          yr[0] = buf[u].x; yr[1] = buf[u].y; yr[2] = buf[u].z; yr[3] = buf[u].w;
-        }
-      }
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < d; j += DIV_THREADS) {
-      float acc = 0.f;
-      for (uint32_t i = 0; i < s; ++i) acc += Y[i * ld + j];
-      mu[j] = acc / (float)s;
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < d; j += DIV_THREADS)
-      for (uint32_t i = 0; i < s; ++i) Y[i * ld + j] -= mu[j];
-  } else {
-    for (int j = threadIdx.x; j < d; j += DIV_THREADS) {
-      float acc = 0.f;
-      for (uint32_t i = 0; i < s; ++i) acc += a.X[(size_t)rows[i] * d + j];
-      mu[j] = acc / (float)s;
-    }
+  for (int j = threadIdx.x; j < d; j += DIV_THREADS) {
+    float acc = 0.f;
+    for (uint32_t i = 0; i < s; ++i) acc += a.X[(size_t)rows[i] * d + j];
+    mu[j] = acc / (float)s;
   }
   __syncthreads();
-  auto yval = [&](uint32_t i, int j) -> float {
-    if constexpr (SAMPLE_LDS) return Y[i * ld + j];
-    else return a.X[(size_t)rows[i] * d + j] - mu[j];
-  };
+  auto yval = [&](uint32_t i, int j) -> float { return a.X[(size_t)rows[i] * d + j] - mu[j]; };
   auto block_sum = [&](float x) -> float {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
     if (lane == 0) red[wv] = x;
@@ -409,17 +563,18 @@ hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s) {
   if ((e = launch_fill_u32(a.hist, 0u, (size_t)a.n_segs * HIST_TOTAL, s)) != hipSuccess) return e;
   if (a.pca_iters > 0 && !a.dirs) {
     size_t base = (size_t)(2 * a.d + 256) * sizeof(float);
-    size_t big = base + (size_t)256 * (a.d + 1) * sizeof(float);
-    if (big <= 150 * 1024) {
+    if (a.d <= PCA_LDS_DMAX) {
+      const int cw = a.d / 4, G = DIV_THREADS / cw;
+      size_t shm = ((size_t)256 * (a.d + 4) + 2 * (size_t)a.d + 256 + (size_t)G * cw * 4) * sizeof(float);
       static bool attr = false;
       if (!attr) {
-        e = hipFuncSetAttribute((const void*)k_pca_dirs<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        e = hipFuncSetAttribute((const void*)k_pca_lds, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
         if (e != hipSuccess) return e;
         attr = true;
       }
-      hipLaunchKernelGGL(k_pca_dirs<true>, dim3(a.n_segs), dim3(DIV_THREADS), big, s, a);
+      hipLaunchKernelGGL(k_pca_lds, dim3(a.n_segs), dim3(DIV_THREADS), shm, s, a);
     } else {
-      hipLaunchKernelGGL(k_pca_dirs<false>, dim3(a.n_segs), dim3(DIV_THREADS), base, s, a);
+      hipLaunchKernelGGL(k_pca_dirs, dim3(a.n_segs), dim3(DIV_THREADS), base, s, a);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
