@@ -66,21 +66,22 @@ __device__ __forceinline__ void list_insert(float (&L)[KP], float x) {
   L[0] = fminf(L[0], x);
 }
 
-// Four canonical distances from one row to four rows (identical arithmetic
-// to dist2_g16 for each pair; the loads of all five rows are in flight together).
-__device__ __forceinline__ void dist2_g16_x4(const float* __restrict__ x, const float* const (&y)[4], int d, int g,
-                                             float (&out)[4]) {
-  float a[4][4];
+// Eight canonical distances: two query rows, four candidates each (dist2_g16's arithmetic per pair).
+__device__ __forceinline__ void dist2_g16_x8(const float* __restrict__ xa, const float* const (&ya)[4],
+                                             const float* __restrict__ xb, const float* const (&yb)[4], int d, int g,
+                                             float (&oa)[4], float (&ob)[4]) {
+  float a[8][4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) a[u][0] = a[u][1] = a[u][2] = a[u][3] = 0.f;
+  for (int u = 0; u < 8; ++u) a[u][0] = a[u][1] = a[u][2] = a[u][3] = 0.f;
   const int nc = d >> 2;
   for (int c = g; c < nc; c += 16) {
-    float4 xv = ((const float4*)x)[c];
-    float4 w[4];
+    float4 xva = ((const float4*)xa)[c], xvb = ((const float4*)xb)[c];
+    float4 w[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) w[u] = ((const float4*)y[u])[c];
+    for (int u = 0; u < 4; ++u) { w[u] = ((const float4*)ya[u])[c]; w[4 + u] = ((const float4*)yb[u])[c]; }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
+      const float4 xv = u < 4 ? xva : xvb;
       float e0 = xv.x - w[u].x, e1 = xv.y - w[u].y, e2 = xv.z - w[u].z, e3 = xv.w - w[u].w;
       a[u][0] = __builtin_fmaf(e0, e0, a[u][0]);
       a[u][1] = __builtin_fmaf(e1, e1, a[u][1]);
@@ -89,13 +90,13 @@ __device__ __forceinline__ void dist2_g16_x4(const float* __restrict__ x, const 
     }
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < 8; ++u) {
     float s = (a[u][0] + a[u][1]) + (a[u][2] + a[u][3]);
     s += __shfl_xor(s, 8, 16);
     s += __shfl_xor(s, 4, 16);
     s += __shfl_xor(s, 2, 16);
     s += __shfl_xor(s, 1, 16);
-    out[u] = s;
+    if (u < 4) oa[u] = s; else ob[u - 4] = s;
   }
 }
 
@@ -423,29 +424,37 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
       }
     }
     wave_sync();
-    // ---- exact re-rank: groups of 16 lanes, four pairs of one query at a time
+    // ---- exact re-rank: groups of 16 lanes, eight pairs (two list blocks) in flight at a time
     {
       const int g = lane >> 4, gl = lane & 15;
-      for (int blk = 0; blk < QPW * KP; blk += 16) {
-        const int qj = blk / KP;
-        const int qp = qbase + qj;
-        const float* xq = a.X + (size_t)S.ids[qp < m ? qp : 0] * d;
-        const float* xc[4];
-        bool ok[4];
-        int ee[4];
+      for (int blk2 = 0; blk2 < QPW * KP; blk2 += 32) {
+        const float* xq[2];
+        const float* xc[2][4];
+        bool ok[2][4];
+        int ee[2][4], qjv[2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          ee[u] = (blk % KP) + g + 4 * u;
-          uint32_t kk = S.lst[w][qj * LS + ee[u]];
-          ok[u] = kk < KEY_VALID && qp < m;
-          int cp = ok[u] ? (int)(kk & POS_MASK) : 0;
-          xc[u] = a.X + (size_t)S.ids[cp] * d;
+        for (int b = 0; b < 2; ++b) {
+          const int blk = blk2 + 16 * b;
+          const int qj = blk / KP;
+          qjv[b] = qj;
+          const int qp = qbase + qj;
+          xq[b] = a.X + (size_t)S.ids[qp < m ? qp : 0] * d;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            ee[b][u] = (blk % KP) + g + 4 * u;
+            uint32_t kk = S.lst[w][qj * LS + ee[b][u]];
+            ok[b][u] = kk < KEY_VALID && qp < m;
+            int cp = ok[b][u] ? (int)(kk & POS_MASK) : 0;
+            xc[b][u] = a.X + (size_t)S.ids[cp] * d;
+          }
         }
-        float dd[4];
-        dist2_g16_x4(xq, xc, d, gl, dd);
+        float dd[2][4];
+        dist2_g16_x8(xq[0], xc[0], xq[1], xc[1], d, gl, dd[0], dd[1]);
         if (gl == 0) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) S.dst[w][qj * LS + ee[u]] = ok[u] ? dd[u] : INF;
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) S.dst[w][qjv[b] * LS + ee[b][u]] = ok[b][u] ? dd[b][u] : INF;
         }
       }
     }
