@@ -123,11 +123,22 @@ __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
       int cc = gl + 16 * i;
       xr[i] = (cc < (d >> 2)) ? ((const float4*)xp)[cc] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    for (int base = 0; base < U; base += 4) {
-      int ci = base + g;
-      uint32_t o = ci < U ? cand_s[w][ci] : (uint32_t)p;
-      float dd = dist2_g16_reg<NCH>(xr, a.X + (size_t)o * d, d, gl);
-      if (gl == 0 && ci < U) cd_s[w][ci] = dd;
+    // four candidates per lane group in flight: base + g + 4j
+    for (int base = 0; base < U; base += 16) {
+      const float* yr[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int ci = base + g + 4 * j;
+        const uint32_t o = ci < U ? cand_s[w][ci] : (uint32_t)p;
+        yr[j] = a.X + (size_t)o * d;
+      }
+      float dd[4];
+      dist2_g16_reg4<NCH>(xr, yr, d, gl, dd);
+      if (gl == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (base + g + 4 * j < U) cd_s[w][base + g + 4 * j] = dd[j];
+      }
     }
   } else {
     for (int base = 0; base < U; base += 4) {

@@ -120,6 +120,44 @@ __device__ __forceinline__ float dist2_g16_reg(const float4 (&xr)[NCH], const fl
   return s;
 }
 
+// dist2_g16_reg for four rows at once (the same arithmetic for each pair);
+// the four rows' loads are in flight together.
+template <int NCH>
+__device__ __forceinline__ void dist2_g16_reg4(const float4 (&xr)[NCH], const float* const (&y)[4], int d, int g,
+                                               float (&out)[4]) {
+  float a[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) a[u][0] = a[u][1] = a[u][2] = a[u][3] = 0.f;
+  const int nc = d >> 2;
+#pragma unroll
+  for (int i = 0; i < NCH; ++i) {
+    const int c = g + 16 * i;
+    if (c < nc) {
+      float4 w[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) w[u] = ((const float4*)y[u])[c];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float4 x = xr[i];
+        float e0 = x.x - w[u].x, e1 = x.y - w[u].y, e2 = x.z - w[u].z, e3 = x.w - w[u].w;
+        a[u][0] = __builtin_fmaf(e0, e0, a[u][0]);
+        a[u][1] = __builtin_fmaf(e1, e1, a[u][1]);
+        a[u][2] = __builtin_fmaf(e2, e2, a[u][2]);
+        a[u][3] = __builtin_fmaf(e3, e3, a[u][3]);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    float s = (a[u][0] + a[u][1]) + (a[u][2] + a[u][3]);
+    s += __shfl_xor(s, 8, 16);
+    s += __shfl_xor(s, 4, 16);
+    s += __shfl_xor(s, 2, 16);
+    s += __shfl_xor(s, 1, 16);
+    out[u] = s;
+  }
+}
+
 // Bitonic sort across the wave of R registers per lane: element e = r*64+lane.
 // Sorts blocks of SEG consecutive elements ascending (SEG = 64*R sorts all).
 template <int R, int SEG, typename K>
