@@ -360,10 +360,15 @@ hipError_t launch_propagate_round(const PropArgs& a, hipStream_t s) {
   if (a.pairwise) {
     if ((e = launch_fill_u32(a.cnt, 0u, (size_t)a.n + 1, s)) != hipSuccess) return e;
   }
+  // R1 registers hold the k^2 gathered ids, R2 the k + k^2 keys of the
+  // final selection: the smallest power-of-two widths that fit
   int kk = a.k * a.k, kt = a.k * a.k + a.k;
   if (kk <= 64 && kt <= 128) e = launch_fwd_d<1, 2>(a, s);
+  else if (kk <= 128 && kt <= 128) e = launch_fwd_d<2, 2>(a, s);
   else if (kk <= 128 && kt <= 256) e = launch_fwd_d<2, 4>(a, s);
+  else if (kk <= 256 && kt <= 256) e = launch_fwd_d<4, 4>(a, s);
   else if (kk <= 256 && kt <= 512) e = launch_fwd_d<4, 8>(a, s);
+  else if (kk <= 512 && kt <= 512) e = launch_fwd_d<8, 8>(a, s);
   else if (kk <= 512 && kt <= 1024) e = launch_fwd_d<8, 16>(a, s);
   else if (kk <= 1024 && kt <= 1024) e = launch_fwd_d<16, 16>(a, s);
   else return hipErrorInvalidValue;
