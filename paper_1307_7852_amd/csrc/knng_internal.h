@@ -101,7 +101,8 @@ struct DiagDev {
   unsigned long long leaf_fallback;    // rows redone exactly (cumulative)
   unsigned long long leaf_rows;        // rows processed (cumulative)
   unsigned long long fallback_count;   // entries in the current leaf fallback list
-  unsigned long long pad;
+  unsigned int exact_flags;            // leaf launch: bit 0 X is FP32-Gram exact, bit 1 BF16-Gram exact
+  unsigned int pad;
   unsigned long long prop_candidates[DIAG_SLOTS];   // last round: sum of |C_p|
   unsigned long long prop_proposals[DIAG_SLOTS];    // last round: proposals kept
 };

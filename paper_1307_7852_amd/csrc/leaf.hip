@@ -52,6 +52,21 @@ struct Cfg {
   static constexpr int LS = KP + 1;         // list stride per query in LDS
 };
 
+// Integer data (every value integral, every norm <= 2^22; for the BF16 Gram
+// also |x| <= 256) makes |x_q|^2 + |x_c|^2 - 2G an exact integer D.  Then
+// the key carries D itself: (min(D, KEY_DSAT) << 11) | position, still a
+// nonnegative float bit pattern below the NaN range (denormals included;
+// the kernels keep them).  A list of such keys is ordered exactly by
+// (distance, position) = (distance, id), so it needs no re-rank; a row whose
+// k-th key is saturated goes to the exact kernel.
+constexpr uint32_t KEY_DSAT = 1044478u;   // (KEY_DSAT << 11) | 2047 < KEY_NONE
+constexpr uint32_t EXACT_FP32 = 1u, EXACT_BF16 = 2u;
+
+__device__ __forceinline__ float make_ikey(float dv, uint32_t pos) {
+  const uint32_t D = (uint32_t)fminf(fmaxf(dv, 0.f), (float)KEY_DSAT);   // dv is an exact integer
+  return __uint_as_float((D << 11) | pos);
+}
+
 __device__ __forceinline__ float make_key(float dv, uint32_t pos) {
   float v = fmaxf(dv, KEY_FLOOR);
   return __uint_as_float((__float_as_uint(v) & ~POS_MASK) | pos);
@@ -154,6 +169,34 @@ struct QFrag {
   }
 };
 
+// Clears bit EXACT_FP32 of *flags if some value of X is not an integer or
+// some row norm exceeds 2^22, and EXACT_BF16 also if some |value| > 256.
+// 16 lanes per row.
+__global__ __launch_bounds__(256) void k_exact_check(const float* __restrict__ X, int64_t n, int d,
+                                                     unsigned int* __restrict__ flags) {
+  const int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
+  const int gl = threadIdx.x & 15;
+  bool integral = true, small = true;
+  float nrm = 0.f;
+  if (row < n) {
+    const float4* xr = (const float4*)(X + row * d);
+    for (int c = gl; c < (d >> 2); c += 16) {
+      const float4 v = xr[c];
+      integral = integral && v.x == rintf(v.x) && v.y == rintf(v.y) && v.z == rintf(v.z) && v.w == rintf(v.w);
+      small = small && fabsf(v.x) <= 256.f && fabsf(v.y) <= 256.f && fabsf(v.z) <= 256.f && fabsf(v.w) <= 256.f;
+      nrm = __builtin_fmaf(v.x, v.x, __builtin_fmaf(v.y, v.y, __builtin_fmaf(v.z, v.z, __builtin_fmaf(v.w, v.w, nrm))));
+    }
+  }
+  nrm += __shfl_xor(nrm, 8, 16);
+  nrm += __shfl_xor(nrm, 4, 16);
+  nrm += __shfl_xor(nrm, 2, 16);
+  nrm += __shfl_xor(nrm, 1, 16);
+  const bool ok32 = integral && !(nrm > 4194304.0f);
+  const bool bad32 = __any(!ok32), bad16 = __any(!(ok32 && small));
+  if ((threadIdx.x & 63) == 0 && (bad32 || bad16))
+    atomicAnd(flags, ~((bad32 ? EXACT_FP32 : 0u) | EXACT_BF16));
+}
+
 // One leaf: members perm[off .. off+m), rows written to ids/dist (already
 // offset to the leaf's division).  `key` names the leaf in the fallback list.
 template <int KC, int KP, bool BF16, int W>
@@ -184,12 +227,17 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     S.flag = 1;
     S.max_n = 0u;
   }
+  // exact integer keys when the whole data set allows them (uniform)
+  const bool ikey = (a.diag->exact_flags & (BF16 ? EXACT_BF16 : EXACT_FP32)) != 0u;
   __syncthreads();
   // ---- BF16: leaf mean, coalesced (threads over features x row groups).
   // A leaf whose values are all integers of magnitude <= 256 is BF16-exact
   // as it stands: then it is not centred (centring would make it inexact),
   // and with norms <= 2^22 its BF16 Gram with FP32 accumulation is exact.
-  if constexpr (BF16) {
+  if (BF16 && ikey) {   // exact as it stands: no centring
+    for (int j = tid; j < d; j += C::THREADS) S.mu[BF16 ? j : 0] = 0.f;
+    __syncthreads();
+  } else if constexpr (BF16) {
     float* part = reinterpret_cast<float*>(&S.tile[0]);   // >= THREADS floats, free until staging
     const int dd = d < C::THREADS ? d : C::THREADS;
     const int G = C::THREADS / dd;
@@ -385,15 +433,22 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
           for (int g = 0; g < 4; ++g) n4[g] = *reinterpret_cast<const float4*>(&S.nrm[c0 + 8 * g + 4 * h]);
           const uint32_t pbase = (uint32_t)(c0 + 4 * h);
           const bool diag = (c0 == qbase);   // uniform: the tile holding the wave's own queries
+          const bool ragged = c0 + TILE > m;  // uniform: the last tile has padding rows
+          auto insert_tile = [&](auto exact_tag) {
+            constexpr bool EXACT = decltype(exact_tag)::value;
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int cl = 8 * (r >> 2) + (r & 3);
-            const float nc = (r & 3) == 0 ? n4[r >> 2].x : (r & 3) == 1 ? n4[r >> 2].y : (r & 3) == 2 ? n4[r >> 2].z : n4[r >> 2].w;
-            const float dv = __builtin_fmaf(-2.0f, acc0[r] + acc1[r], nq + nc);
-            float x = make_key(dv, pbase + (uint32_t)cl);
-            if (diag && (cl + 4 * h == r32)) x = __uint_as_float(KEY_NONE);
-            list_insert<KP>(Lk, x);
-          }
+            for (int r = 0; r < 16; ++r) {
+              const int cl = 8 * (r >> 2) + (r & 3);
+              const float nc = (r & 3) == 0 ? n4[r >> 2].x : (r & 3) == 1 ? n4[r >> 2].y : (r & 3) == 2 ? n4[r >> 2].z : n4[r >> 2].w;
+              const float dv = __builtin_fmaf(-2.0f, acc0[r] + acc1[r], nq + nc);
+              float x = EXACT ? make_ikey(dv, pbase + (uint32_t)cl) : make_key(dv, pbase + (uint32_t)cl);
+              if (diag && (cl + 4 * h == r32)) x = __uint_as_float(KEY_NONE);
+              if (EXACT && ragged && (int)pbase + cl >= m) x = __uint_as_float(KEY_NONE);
+              list_insert<KP>(Lk, x);
+            }
+          };
+          if (ikey) insert_tile(std::true_type{});
+          else insert_tile(std::false_type{});
         }
       }
       if (more) stage_store(st + 1, buf ^ 1, rg, first);
@@ -417,6 +472,31 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
             Lk[j + s] = hi;
           }
         }
+      }
+      if (ikey) {
+        // exact keys: the merged list is the answer in (distance, id) order;
+        // the two lanes of a query write alternate slots
+        if (qok) {
+          const uint32_t qid = S.ids[qpos];
+#pragma unroll
+          for (int j = 0; j < KP; ++j) {
+            if (j < k && (j & 1) == h) {
+              const uint32_t kk = __float_as_uint(Lk[j]);
+              const bool none = kk == KEY_NONE;
+              ids_out[(size_t)qid * k + j] = none ? KNNG_NONE : S.ids[kk & POS_MASK];
+              dist_out[(size_t)qid * k + j] = none ? INF : (float)(kk >> 11);
+              if (j == k - 1 && !none && (kk >> 11) >= KEY_DSAT) {   // saturated: order not exact
+                unsigned long long sl = atomicAdd(&a.diag->fallback_count, 1ull);
+                atomicAdd(&a.diag->leaf_fallback, 1ull);
+                if (sl < a.fallback_cap) {
+                  a.fallback[2 * sl] = L;
+                  a.fallback[2 * sl + 1] = (uint32_t)qpos;
+                }
+              }
+            }
+          }
+        }
+        continue;
       }
       if (h == 0) {
 #pragma unroll
@@ -701,6 +781,12 @@ hipError_t launch_leaf(const LeafArgs& a, hipStream_t s) {
   hipError_t e;
   if (a.prepare_only) return a.precision == KNNG_BF16 ? launch_leaf_kc<true>(a, s) : launch_leaf_kc<false>(a, s);
   if ((e = launch_fill_u32((uint32_t*)&a.diag->fallback_count, 0u, 2, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(&a.diag->exact_flags, EXACT_FP32 | EXACT_BF16, 1, s)) != hipSuccess) return e;
+  if (a.n > 0) {
+    hipLaunchKernelGGL(k_exact_check, dim3((unsigned)((a.n * 16 + 255) / 256)), dim3(256), 0, s, a.X, a.n, a.d,
+                       &a.diag->exact_flags);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   e = a.precision == KNNG_BF16 ? launch_leaf_kc<true>(a, s) : launch_leaf_kc<false>(a, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_leaf_exact, dim3(1024), dim3(256), 0, s, a);

@@ -205,6 +205,27 @@ def test_leaf_knn_parity(dev, case):
         assert np.array_equal(gd[gi != NONE].astype(np.float64), od[oi != NONE])
 
 
+@pytest.mark.parametrize("prec", [K.FP32, K.BF16])
+def test_leaf_integer_keys_saturate_to_exact_rows(dev, prec):
+    """Uniform integers in [0, 255] at d = 128: neighbour distances (~1.4e6)
+    exceed what an exact integer key holds, so rows go to the exact kernel;
+    the lists must still be the oracle's."""
+    say("leaf saturated integer keys", prec)
+    n, d, k = 3000, 128, 8
+    X = np.random.default_rng(77).integers(0, 256, size=(n, d)).astype(np.float32)
+    kp, op = _params(n, d, k, T=1, leaf_max=256, precision=prec, seed=4)
+    X_t = torch.from_numpy(X).to(dev)
+    perm, leaf_off, perm_h, off_h, _ = gpu_divide(kp, X_t, 0, dev)
+    _, _, gi, gd, diag = gpu_leaf(kp, X_t, perm, leaf_off, len(off_h) - 1, dev)
+    perm_o, off_o, _ = O.divide(X, op, 0)
+    assert np.array_equal(perm_h, perm_o)
+    oi, od = O.leaf_knn(X, perm_o, off_o, k)
+    swaps = compare_rows(X, gi, gd, oi, range(n))
+    say(f"  swaps={swaps} fallback_rows={diag['leaf_rows_fallback']} of {diag['leaf_rows']}")
+    assert diag["leaf_rows_fallback"] > n // 2
+    assert swaps == 0 and np.array_equal(gi, oi)
+
+
 def test_leaf_larger_than_max_uses_exact_rows(dev):
     say("leaf > max")
     n, d, k = 3000, 16, 7
