@@ -81,6 +81,16 @@ __device__ __forceinline__ void list_insert(float (&L)[KP], float x) {
   L[0] = fminf(L[0], x);
 }
 
+// The same on the first KI entries only (the rest keep what they hold):
+// enough wherever only the KI smallest keys are ever read.
+template <int KI, int KP>
+__device__ __forceinline__ void list_insert_head(float (&L)[KP], float x) {
+  static_assert(KI <= KP, "head longer than the list");
+#pragma unroll
+  for (int j = KI - 1; j > 0; --j) L[j] = __builtin_amdgcn_fmed3f(L[j - 1], x, L[j]);
+  L[0] = fminf(L[0], x);
+}
+
 // Eight canonical distances: two query rows, four candidates each (dist2_g16's arithmetic per pair).
 __device__ __forceinline__ void dist2_g16_x8(const float* __restrict__ xa, const float* const (&ya)[4],
                                              const float* __restrict__ xb, const float* const (&yb)[4], int d, int g,
@@ -277,19 +287,25 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
   const int ntile = (m + TILE - 1) / TILE;
   const int nsteps = ntile * nchunk;
 
-  // global -> registers for step st (tile st / nchunk, chunk st % nchunk)
+  // global -> registers for step st (tile st / nchunk, chunk st % nchunk).
+  // Every thread issues all STAGE_F4 loads unconditionally, so the number of
+  // loads in flight is fixed and the Gram's MFMAs need not wait for this
+  // prefetch: rows past the leaf repeat its last member (the padding norm
+  // keeps them out of every list) and features past d are zeroed by a
+  // multiply, not a select, which the compiler would turn into a branch
+  // around the load.
   auto stage_load = [&](int st, float4 (&rg)[STAGE_F4]) {
     int c0 = (st / nchunk) * TILE, kc = (st % nchunk) * KC;
 #pragma unroll
     for (int u = 0; u < STAGE_F4; ++u) {
       int e = tid + u * C::THREADS;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (e < TILE_F4) {
-        int row = e / F4_PER_ROW, col = (e % F4_PER_ROW) * 4;
-        int cp = c0 + row;
-        if (cp < m && kc + col < d) v = *(const float4*)(a.X + (size_t)S.ids[cp] * d + kc + col);
-      }
-      rg[u] = v;
+      int row = e / F4_PER_ROW, col = (e % F4_PER_ROW) * 4;
+      int cp = c0 + row;
+      const bool colok = e < TILE_F4 && kc + col < d;
+      const int cpc = cp < m ? cp : m - 1;
+      const float keep = colok ? 1.0f : 0.0f;
+      const float4 v = *(const float4*)(a.X + (size_t)S.ids[cpc] * d + (colok ? kc + col : 0));
+      rg[u] = make_float4(v.x * keep, v.y * keep, v.z * keep, v.w * keep);
     }
   };
   // registers -> LDS; on the first pass also the member norms (rows of a
@@ -398,11 +414,16 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     for (int st = 0; st < nsteps; ++st) {
       const int buf = st & 1;
       const int c0 = (st / nchunk) * TILE, kci = st % nchunk;
+      // the query chunk is loaded before the next tile's prefetch so that the
+      // MFMAs wait only for the older loads and the prefetch stays in flight
+      if (wave_on && nchunk > 1) qf.load(qrow, kci * KC, d, h, S.mu, qok);
       float4 rg[STAGE_F4];
+      // the last step re-stages its own tile into the idle buffer, so every
+      // step issues the same loads
       const bool more = st + 1 < nsteps;
-      if (more) stage_load(st + 1, rg);
+      const int nxt = more ? st + 1 : st;
+      stage_load(nxt, rg);
       if (wave_on) {
-        if (nchunk > 1) qf.load(qrow, kci * KC, d, h, S.mu, qok);
         if (kci == 0) {
 #pragma unroll
           for (int r = 0; r < 16; ++r) { acc0[r] = 0.f; acc1[r] = 0.f; }
@@ -434,24 +455,45 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
           const uint32_t pbase = (uint32_t)(c0 + 4 * h);
           const bool diag = (c0 == qbase);   // uniform: the tile holding the wave's own queries
           const bool ragged = c0 + TILE > m;  // uniform: the last tile has padding rows
-          auto insert_tile = [&](auto exact_tag) {
+          // EXACT: integer keys; EDGE: the tile needs the self-pair or padding
+          // masks; KI: list entries kept (integer keys need only the k smallest)
+          auto insert_tile = [&](auto exact_tag, auto edge_tag, auto len_tag) {
             constexpr bool EXACT = decltype(exact_tag)::value;
+            constexpr bool EDGE = decltype(edge_tag)::value;
+            constexpr int KI = decltype(len_tag)::value;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
               const int cl = 8 * (r >> 2) + (r & 3);
               const float nc = (r & 3) == 0 ? n4[r >> 2].x : (r & 3) == 1 ? n4[r >> 2].y : (r & 3) == 2 ? n4[r >> 2].z : n4[r >> 2].w;
               const float dv = __builtin_fmaf(-2.0f, acc0[r] + acc1[r], nq + nc);
               float x = EXACT ? make_ikey(dv, pbase + (uint32_t)cl) : make_key(dv, pbase + (uint32_t)cl);
-              if (diag && (cl + 4 * h == r32)) x = __uint_as_float(KEY_NONE);
-              if (EXACT && ragged && (int)pbase + cl >= m) x = __uint_as_float(KEY_NONE);
-              list_insert<KP>(Lk, x);
+              if constexpr (EDGE) {
+                if (diag && (cl + 4 * h == r32)) x = __uint_as_float(KEY_NONE);
+                if (EXACT && ragged && (int)pbase + cl >= m) x = __uint_as_float(KEY_NONE);
+              }
+              list_insert_head<KI>(Lk, x);
             }
           };
-          if (ikey) insert_tile(std::true_type{});
-          else insert_tile(std::false_type{});
+          using T_ = std::true_type;
+          using F_ = std::false_type;
+          using KFull = std::integral_constant<int, KP>;
+          using KHalf = std::integral_constant<int, KP / 2>;
+          using K3q = std::integral_constant<int, KP - KP / 4>;
+          if (ikey) {
+            const bool edge = diag || ragged;
+            if (k <= KP / 2) {
+              if (edge) insert_tile(T_{}, T_{}, KHalf{}); else insert_tile(T_{}, F_{}, KHalf{});
+            } else if (k <= KP - KP / 4) {
+              if (edge) insert_tile(T_{}, T_{}, K3q{}); else insert_tile(T_{}, F_{}, K3q{});
+            } else {
+              if (edge) insert_tile(T_{}, T_{}, KFull{}); else insert_tile(T_{}, F_{}, KFull{});
+            }
+          } else {
+            if (diag) insert_tile(F_{}, T_{}, KFull{}); else insert_tile(F_{}, F_{}, KFull{});
+          }
         }
       }
-      if (more) stage_store(st + 1, buf ^ 1, rg, first);
+      stage_store(nxt, buf ^ 1, rg, first && more);
       __syncthreads();
     }
     if (!wave_on) continue;                   // no barrier below this point
