@@ -260,13 +260,14 @@ int divide_layout(const knng_params& p, int t, DivideLayout& L) {
   return KNNG_OK;
 }
 
-// leaf scratch: fallback list + work counter
-struct LeafLayout { size_t diag, fallback, counter, total; };
+// leaf scratch: fallback list + work counter + per-point norms
+struct LeafLayout { size_t diag, fallback, counter, pnorm, total; };
 LeafLayout leaf_layout(const knng_params& p, int slots) {
   LeafLayout L; Carve c;
   L.diag = c.take(sizeof(DiagDev));
   L.fallback = c.take((size_t)slots * p.n * 2 * 4);
   L.counter = c.take(64);
+  L.pnorm = c.take((size_t)p.n * 4);
   L.total = c.off;
   return L;
 }
@@ -426,6 +427,7 @@ int leaf_single(const knng_params& p, const float* X, const uint32_t* perm, cons
   a.ids = ids; a.dist = dist;
   a.fallback = (uint32_t*)(scratch + L.fallback);
   a.fallback_cap = (uint64_t)p.n;
+  a.pnorm = (float*)(scratch + L.pnorm);
   a.diag = diag;
   apply_tune(p, 2 * (int64_t)p.leaf_max, a);
   HIP_TRY(launch_leaf(a, s));
@@ -446,6 +448,7 @@ int leaf_batched(const knng_params& p, const Batch& B, const char* blob_dev, con
   a.grid = (uint32_t)cu_count();
   a.fallback = (uint32_t*)(scratch + L.fallback);
   a.fallback_cap = (uint64_t)B.slots * p.n;
+  a.pnorm = (float*)(scratch + L.pnorm);
   a.diag = diag;
   if (waves < 0) {
     apply_tune(p, B.work.empty() ? 1 : (int64_t)B.work[0].m, a);   // the work list is largest first

@@ -137,6 +137,7 @@ struct LeafArgs {
   uint32_t* counter;         // batched mode: next work item (zeroed by the launcher)
   uint32_t grid;             // batched mode: workgroups launched
   uint32_t* fallback;        // (leaf or work index, position) pairs, capacity fallback_cap
+  float* pnorm;              // n per-point squared norms, written by the launch before the leaves run
   uint64_t fallback_cap;
   DiagDev* diag;
   int waves;                 // workgroup waves (4 or 8; 0: the default for kp)

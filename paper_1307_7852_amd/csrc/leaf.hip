@@ -140,11 +140,11 @@ template <int KC, int KP, bool BF16, int W>
 struct LeafShared {
   using C = Cfg<KP, W>;
   uint32_t ids[KNNG_MAX_LEAF];
-  float nrm[KNNG_MAX_LEAF];                 // member norms (BF16: of the rounded centred rows)
+  float nrm[KNNG_MAX_LEAF];                 // member norms (centred BF16: of the rounded centred rows)
   TileT<KC, BF16> tile[2];
   float mu[BF16 ? MU_MAX : 1];
   uint32_t max_n;                           // largest member norm (float bits)
-  int flag;                                 // FP32: every value integral and every norm <= 2^22
+  int flag;                                 // every value integral and every norm <= 2^22 (BF16: |value| <= 256)
   float qn[C::WAVES][QPW];                  // query norms, as used in the keys
   uint32_t lst[C::WAVES][QPW * C::LS];      // merged top-KP keys per query
   float dst[C::WAVES][QPW * C::LS];         // their canonical distances
@@ -181,9 +181,11 @@ struct QFrag {
 
 // Clears bit EXACT_FP32 of *flags if some value of X is not an integer or
 // some row norm exceeds 2^22, and EXACT_BF16 also if some |value| > 256.
+// Writes every row's squared norm to pnorm, with the sign bit set when the
+// row holds a non-integer (the leaf kernel reads both from there).
 // 16 lanes per row.
 __global__ __launch_bounds__(256) void k_exact_check(const float* __restrict__ X, int64_t n, int d,
-                                                     unsigned int* __restrict__ flags) {
+                                                     unsigned int* __restrict__ flags, float* __restrict__ pnorm) {
   const int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
   const int gl = threadIdx.x & 15;
   bool integral = true, small = true;
@@ -201,6 +203,10 @@ __global__ __launch_bounds__(256) void k_exact_check(const float* __restrict__ X
   nrm += __shfl_xor(nrm, 4, 16);
   nrm += __shfl_xor(nrm, 2, 16);
   nrm += __shfl_xor(nrm, 1, 16);
+  // the row is integral when all 16 lanes of its group found only integers
+  const unsigned long long nonint = __ballot(!integral);
+  const bool row_int = ((nonint >> (threadIdx.x & 48)) & 0xFFFFull) == 0ull;
+  if (row < n && gl == 0) pnorm[row] = row_int ? nrm : -nrm;
   const bool ok32 = integral && !(nrm > 4194304.0f);
   const bool bad32 = __any(!ok32), bad16 = __any(!(ok32 && small));
   if ((threadIdx.x & 63) == 0 && (bad32 || bad16))
@@ -276,6 +282,28 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
       __syncthreads();
     }
   }
+  // Member norms of uncentred rows come from the per-point norms (sign bit:
+  // the row holds a non-integer); padding rows up to the tile boundary get
+  // PAD_NORM.  Centred BF16 rows get theirs while the first pass stages them.
+  const bool pre_norms = !BF16 || ikey;   // uniform
+  if (pre_norms) {
+    const int mt = (m + TILE - 1) / TILE * TILE;
+    float mx = 0.f;
+    bool bad = false;
+    for (int i = tid; i < mt; i += C::THREADS) {
+      float v = PAD_NORM;
+      if (i < m) {
+        const float pn = a.pnorm[S.ids[i]];
+        v = fabsf(pn);
+        bad = bad || (__float_as_uint(pn) >> 31) != 0u || v > 4194304.0f;   // 2^22: partial Gram sums stay exact
+        mx = fmaxf(mx, v);
+      }
+      S.nrm[i] = v;
+    }
+    if (__any(bad) && lane == 0) S.flag = 0;
+    atomicMax(&S.max_n, __float_as_uint(mx));
+    __syncthreads();
+  }
   const float eps_c = 2.0f * (float)(d + 4) * 5.9604645e-8f;   // 2 (d+4) 2^-24
   const float INF = __int_as_float(0x7F800000);
 
@@ -308,8 +336,9 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
       rg[u] = make_float4(v.x * keep, v.y * keep, v.z * keep, v.w * keep);
     }
   };
-  // registers -> LDS; on the first pass also the member norms (rows of a
-  // tile are held by F4_PER_ROW consecutive lanes, reduced by shuffles)
+  // registers -> LDS; on the first pass of a centred BF16 leaf also the
+  // member norms (rows of a tile are held by F4_PER_ROW consecutive lanes,
+  // reduced by shuffles)
   auto stage_store = [&](int st, int buf, const float4 (&rg)[STAGE_F4], bool norms) {
     int c0 = (st / nchunk) * TILE, kci = st % nchunk, kc = kci * KC;
 #pragma unroll
@@ -321,7 +350,6 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
       if constexpr (!BF16) {
         if (e < TILE_F4) *(float4*)&S.tile[buf].v[row * Tile::STRIDE + col] = v;
         sq = __builtin_fmaf(v.x, v.x, __builtin_fmaf(v.y, v.y, __builtin_fmaf(v.z, v.z, v.w * v.w)));
-        if (norms && (v.x != rintf(v.x) || v.y != rintf(v.y) || v.z != rintf(v.z) || v.w != rintf(v.w))) S.flag = 0;
       } else {
         bool in = e < TILE_F4 && kc + col < d;   // padded features stay exactly zero
         float t0 = in ? bf16_round(v.x - S.mu[kc + col]) : 0.f;
@@ -408,7 +436,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     {
       float4 rg[STAGE_F4];
       stage_load(0, rg);
-      stage_store(0, 0, rg, first);
+      stage_store(0, 0, rg, first && !pre_norms);
     }
     __syncthreads();
     for (int st = 0; st < nsteps; ++st) {
@@ -493,7 +521,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
           }
         }
       }
-      stage_store(nxt, buf ^ 1, rg, first && more);
+      stage_store(nxt, buf ^ 1, rg, first && more && !pre_norms);
       __syncthreads();
     }
     if (!wave_on) continue;                   // no barrier below this point
@@ -826,7 +854,7 @@ hipError_t launch_leaf(const LeafArgs& a, hipStream_t s) {
   if ((e = launch_fill_u32(&a.diag->exact_flags, EXACT_FP32 | EXACT_BF16, 1, s)) != hipSuccess) return e;
   if (a.n > 0) {
     hipLaunchKernelGGL(k_exact_check, dim3((unsigned)((a.n * 16 + 255) / 256)), dim3(256), 0, s, a.X, a.n, a.d,
-                       &a.diag->exact_flags);
+                       &a.diag->exact_flags, a.pnorm);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   e = a.precision == KNNG_BF16 ? launch_leaf_kc<true>(a, s) : launch_leaf_kc<false>(a, s);
