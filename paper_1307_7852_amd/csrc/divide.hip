@@ -130,6 +130,58 @@ __device__ __forceinline__ float dot_seq(const float* __restrict__ x, const floa
   return acc;
 }
 
+// Four bytes of the one-byte copy of X as the float4 of X they hold.
+__device__ __forceinline__ float4 bytes4(uint32_t b) {
+  return make_float4((float)(b & 0xFFu), (float)((b >> 8) & 0xFFu), (float)((b >> 16) & 0xFFu), (float)(b >> 24));
+}
+
+// dot_seq on a row of the one-byte copy: the same values in the same order,
+// so the same result.  A 128-value block (eight 16-byte loads, the whole row
+// at d = 128) is in flight at once, a quarter of the float row's bytes.
+__device__ __forceinline__ float dot_seq_u8(const uint8_t* __restrict__ x, const float* __restrict__ a, int d) {
+#pragma clang fp contract(off)
+  float acc = 0.f;
+  const int c4 = d >> 2;
+  int c = 0;
+  auto quad = [&](uint32_t wb, int cc) {
+    const float4 u = bytes4(wb);
+    const float* ak = a + 4 * cc;
+    float p0 = u.x * ak[0];
+    acc = acc + p0;
+    float p1 = u.y * ak[1];
+    acc = acc + p1;
+    float p2 = u.z * ak[2];
+    acc = acc + p2;
+    float p3 = u.w * ak[3];
+    acc = acc + p3;
+  };
+  if ((d & 15) == 0) {
+    const uint4* xv = (const uint4*)x;
+    for (; c + 32 <= c4; c += 32) {
+      uint4 w[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) w[k] = xv[c / 4 + k];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        quad(w[k].x, c + 4 * k);
+        quad(w[k].y, c + 4 * k + 1);
+        quad(w[k].z, c + 4 * k + 2);
+        quad(w[k].w, c + 4 * k + 3);
+      }
+    }
+  }
+  const uint32_t* xw = (const uint32_t*)x;
+  for (; c + 8 <= c4; c += 8) {
+    uint32_t w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = xw[c + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) quad(w[k], c + k);
+  }
+  for (; c < c4; ++c) quad(xw[c], c);
+  return acc;
+}
+
 // --------------------------------------------------------------- kernels
 __global__ __launch_bounds__(DIV_THREADS) void k_proj_hist0(DivideLevelArgs a) {
   extern __shared__ float dir[];
@@ -139,10 +191,11 @@ __global__ __launch_bounds__(DIV_THREADS) void k_proj_hist0(DivideLevelArgs a) {
   for (int b = threadIdx.x; b < (int)HIST_B0; b += DIV_THREADS) lh[b] = 0;
   load_direction(a, sd, dir, it.start == sd.off);
   const size_t base = (size_t)it.slot * (size_t)a.n;
+  const bool u8 = a.X8 && (*a.flags & EXACT_U8) != 0u;   // uniform
   for (uint32_t i = threadIdx.x; i < it.len; i += DIV_THREADS) {
     size_t pos = base + it.start + i;
     uint32_t row = a.perm_in[pos];
-    float key = dot_seq(a.X + (size_t)row * a.d, dir, a.d);
+    float key = u8 ? dot_seq_u8(a.X8 + (size_t)row * a.d, dir, a.d) : dot_seq(a.X + (size_t)row * a.d, dir, a.d);
     uint32_t uk = ordered_key(key);
     a.ukeys[pos] = uk;
     atomicAdd(&lh[uk >> 21], 1u);
@@ -293,15 +346,28 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
   }
   for (int j = tid; j < d; j += DIV_THREADS) v[j] = rp_entry(a.seed, sd.t, sd.v, (uint32_t)j);
   __syncthreads();
-  // raw sample -> LDS, 8 loads in flight per thread
+  // raw sample -> LDS, 8 loads in flight per thread (from the one-byte
+  // copy when it holds X)
   {
     const int tot = (int)s * cw;
+    const bool u8 = a.X8 && (*a.flags & EXACT_U8) != 0u;   // uniform
     for (int e0 = tid; e0 < tot; e0 += DIV_THREADS * 8) {
       float4 buf[8];
+      if (u8) {
+        uint32_t wb[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        int e = e0 + u * DIV_THREADS;
-        buf[u] = e < tot ? ((const float4*)(a.X + (size_t)rows[e / cw] * d))[e % cw] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int u = 0; u < 8; ++u) {
+          int e = e0 + u * DIV_THREADS;
+          wb[u] = e < tot ? ((const uint32_t*)(a.X8 + (size_t)rows[e / cw] * d))[e % cw] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) buf[u] = bytes4(wb[u]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          int e = e0 + u * DIV_THREADS;
+          buf[u] = e < tot ? ((const float4*)(a.X + (size_t)rows[e / cw] * d))[e % cw] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {

@@ -293,8 +293,9 @@ PropLayout prop_layout(const knng_params& p) {
 }
 
 // knng_build: diag | plan blob | T lists | two T-slot permutation buffers |
-// one region shared in turn by the divide, leaf and propagation scratch
-struct BuildLayout { size_t diag, blob, lists_ids, lists_dist, permA, permB, shared, total; };
+// per-point norms | one-byte copy of X | one region shared in turn by the
+// divide, leaf and propagation scratch
+struct BuildLayout { size_t diag, blob, lists_ids, lists_dist, permA, permB, pnorm, x8, shared, total; };
 int build_layout(const knng_params& p, BuildLayout& L) {
   int st;
   BatchPtr B = get_batch(p, all_divisions(p), &st);
@@ -307,6 +308,8 @@ int build_layout(const knng_params& p, BuildLayout& L) {
   L.lists_dist = c.take(nk * 4 * p.T);
   L.permA = c.take((size_t)p.n * 4 * p.T);
   L.permB = c.take((size_t)p.n * 4 * p.T);
+  L.pnorm = c.take((size_t)p.n * 4);
+  L.x8 = c.take((size_t)p.n * p.d);
   size_t sh = std::max({div_scratch(p, *B).total, leaf_layout(p, p.T).total, prop_layout(p).total});
   L.shared = c.take(sh);
   L.total = c.off;
@@ -352,7 +355,8 @@ int cu_count() {
 // blob_dev.  buf[0] receives the identity; the final permutations land in
 // buf[depth % 2].
 int divide_core(const knng_params& p, const Batch& B, const char* blob_dev, const float* X, const float* dir_override,
-                float* dirs_out, uint32_t* buf0, uint32_t* buf1, char* scratch, hipStream_t s) {
+                float* dirs_out, uint32_t* buf0, uint32_t* buf1, char* scratch, hipStream_t s,
+                const uint8_t* x8 = nullptr, const uint32_t* flags = nullptr) {
   DivScratch L = div_scratch(p, B);
   uint32_t* ukeys = (uint32_t*)(scratch + L.ukeys);
   uint32_t* hist = (uint32_t*)(scratch + L.hist);
@@ -376,6 +380,8 @@ int divide_core(const knng_params& p, const Batch& B, const char* blob_dev, cons
     a.dirs_out = dirs_out;
     a.pca_iters = (p.split == KNNG_SPLIT_PCA && !dir_override) ? p.pca_iters : 0;
     a.pca_dirs = pca;
+    a.X8 = x8;
+    a.flags = flags;
     HIP_TRY(launch_divide_level(a, s));
   }
   return KNNG_OK;
@@ -436,7 +442,7 @@ int leaf_single(const knng_params& p, const float* X, const uint32_t* perm, cons
 
 int leaf_batched(const knng_params& p, const Batch& B, const char* blob_dev, const float* X, const uint32_t* perms,
                  uint32_t* ids, float* dist, char* scratch, DiagDev* diag, hipStream_t s, int waves = -1, int kc = -1,
-                 bool prepare_only = false) {
+                 bool prepare_only = false, float* pnorm_checked = nullptr) {
   LeafLayout L = leaf_layout(p, B.slots);
   LeafArgs a{};
   a.X = X; a.n = p.n; a.d = p.d; a.k = p.k; a.kp = p.k + p.rerank_m; a.precision = p.precision;
@@ -448,7 +454,8 @@ int leaf_batched(const knng_params& p, const Batch& B, const char* blob_dev, con
   a.grid = (uint32_t)cu_count();
   a.fallback = (uint32_t*)(scratch + L.fallback);
   a.fallback_cap = (uint64_t)B.slots * p.n;
-  a.pnorm = (float*)(scratch + L.pnorm);
+  a.pnorm = pnorm_checked ? pnorm_checked : (float*)(scratch + L.pnorm);
+  a.data_checked = pnorm_checked != nullptr;
   a.diag = diag;
   if (waves < 0) {
     apply_tune(p, B.work.empty() ? 1 : (int64_t)B.work[0].m, a);   // the work list is largest first
@@ -766,17 +773,23 @@ static int build_impl(const knng_params* p, const float* X, const float* S, int 
   DiagDev* diag = (DiagDev*)(w + BL.diag);
   HIP_TRY(zero_diag(diag, s));
   auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord((*ev)[i], s) : hipSuccess; };
+  float* pnorm = (float*)(w + BL.pnorm);
+  uint8_t* x8 = (uint8_t*)(w + BL.x8);
   uint32_t* permA = (uint32_t*)(w + BL.permA);
   uint32_t* permB = (uint32_t*)(w + BL.permB);
   uint32_t* lists_ids = (uint32_t*)(w + BL.lists_ids);
   float* lists_dist = (float*)(w + BL.lists_dist);
   char* sh = w + BL.shared;
   HIP_TRY(mark(0));
-  st = divide_core(ps, *B, w + BL.blob, S, nullptr, nullptr, permA, permB, sh, s);
+  // one check of X serves every stage: exactness flags, row norms and the
+  // one-byte copy that the divide and propagation read when it holds X
+  HIP_TRY(launch_data_check(X, p->n, p->d, &diag->exact_flags, pnorm, x8, s));
+  st = divide_core(ps, *B, w + BL.blob, S, nullptr, nullptr, permA, permB, sh, s, (S == X && ds == p->d) ? x8 : nullptr,
+                   &diag->exact_flags);
   if (st) return st;
   const uint32_t* perms = (B->depth % 2 == 0) ? permA : permB;
   HIP_TRY(mark(1));
-  st = leaf_batched(*p, *B, w + BL.blob, X, perms, lists_ids, lists_dist, sh, diag, s);
+  st = leaf_batched(*p, *B, w + BL.blob, X, perms, lists_ids, lists_dist, sh, diag, s, -1, -1, false, pnorm);
   if (st) return st;
   HIP_TRY(mark(2));
   HIP_TRY(launch_merge(p->n, p->k, p->T, lists_ids, lists_dist, ids, dist, s));

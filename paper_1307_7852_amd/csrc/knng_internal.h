@@ -95,6 +95,12 @@ struct Carve {
 };
 
 // Device diagnostics block (start of every workspace).
+// Bits of DiagDev::exact_flags, set by the data check of a launch:
+// EXACT_FP32: every value of X an integer and every row norm <= 2^22;
+// EXACT_BF16: also every |value| <= 256; EXACT_U8: every value one of
+// 0, 1, ..., 255 (then a one-byte copy of X holds X, up to the sign of zero).
+constexpr uint32_t EXACT_FP32 = 1u, EXACT_BF16 = 2u, EXACT_U8 = 4u;
+
 // Counters that many blocks bump are spread over DIAG_SLOTS addresses.
 constexpr int DIAG_SLOTS = 64;
 struct DiagDev {
@@ -125,6 +131,8 @@ struct DivideLevelArgs {
   float* dirs_out;           // nullable
   int pca_iters;             // > 0: compute principal directions into pca_dirs
   float* pca_dirs;           // n_internal x d scratch when PCA
+  const uint8_t* X8;         // nullable: one-byte copy of X, read instead of X when *flags has EXACT_U8
+  const uint32_t* flags;
 };
 hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s);
 
@@ -137,14 +145,21 @@ struct LeafArgs {
   uint32_t* counter;         // batched mode: next work item (zeroed by the launcher)
   uint32_t grid;             // batched mode: workgroups launched
   uint32_t* fallback;        // (leaf or work index, position) pairs, capacity fallback_cap
-  float* pnorm;              // n per-point squared norms, written by the launch before the leaves run
+  float* pnorm;              // n per-point squared norms, written by the data check
   uint64_t fallback_cap;
   DiagDev* diag;
   int waves;                 // workgroup waves (4 or 8; 0: the default for kp)
   int kc;                    // feature chunk staged per tile (32, 64, 128; 0: chosen from d)
   bool prepare_only;         // set kernel attributes and occupancy, launch nothing
+  bool data_checked;         // diag->exact_flags and pnorm already hold this X's check
 };
 hipError_t launch_leaf(const LeafArgs& a, hipStream_t s);
+// Data check of X: clears the EXACT_* bits of *flags (set them all first)
+// that some value or row norm rules out, writes the n row norms to pnorm
+// (sign bit set for a row holding a non-integer) and, when x8 is not null,
+// the one-byte copy of X (meaningful only when EXACT_U8 stays set).
+hipError_t launch_data_check(const float* X, int64_t n, int d, uint32_t* flags, float* pnorm, uint8_t* x8,
+                             hipStream_t s);
 
 hipError_t launch_merge(int64_t n, int k, int n_lists, const uint32_t* ids_in, const float* dist_in,
                         uint32_t* ids_out, float* dist_out, hipStream_t s);

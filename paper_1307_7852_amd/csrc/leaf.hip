@@ -60,7 +60,6 @@ struct Cfg {
 // (distance, position) = (distance, id), so it needs no re-rank; a row whose
 // k-th key is saturated goes to the exact kernel.
 constexpr uint32_t KEY_DSAT = 1044478u;   // (KEY_DSAT << 11) | 2047 < KEY_NONE
-constexpr uint32_t EXACT_FP32 = 1u, EXACT_BF16 = 2u;
 
 __device__ __forceinline__ float make_ikey(float dv, uint32_t pos) {
   const uint32_t D = (uint32_t)fminf(fmaxf(dv, 0.f), (float)KEY_DSAT);   // dv is an exact integer
@@ -180,15 +179,17 @@ struct QFrag {
 };
 
 // Clears bit EXACT_FP32 of *flags if some value of X is not an integer or
-// some row norm exceeds 2^22, and EXACT_BF16 also if some |value| > 256.
-// Writes every row's squared norm to pnorm, with the sign bit set when the
-// row holds a non-integer (the leaf kernel reads both from there).
-// 16 lanes per row.
+// some row norm exceeds 2^22, EXACT_BF16 also if some |value| > 256, and
+// EXACT_U8 if some value is not one of 0, 1, ..., 255 (-0 counts as 0: a
+// zero's sign never changes a sum that starts from +0, so the byte copy's +0
+// gives the same projections).  Writes every row's
+// squared norm to pnorm, with the sign bit set when the row holds a
+// non-integer.  16 lanes per row.
 __global__ __launch_bounds__(256) void k_exact_check(const float* __restrict__ X, int64_t n, int d,
                                                      unsigned int* __restrict__ flags, float* __restrict__ pnorm) {
   const int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
   const int gl = threadIdx.x & 15;
-  bool integral = true, small = true;
+  bool integral = true, small = true, byte = true;
   float nrm = 0.f;
   if (row < n) {
     const float4* xr = (const float4*)(X + row * d);
@@ -196,6 +197,8 @@ __global__ __launch_bounds__(256) void k_exact_check(const float* __restrict__ X
       const float4 v = xr[c];
       integral = integral && v.x == rintf(v.x) && v.y == rintf(v.y) && v.z == rintf(v.z) && v.w == rintf(v.w);
       small = small && fabsf(v.x) <= 256.f && fabsf(v.y) <= 256.f && fabsf(v.z) <= 256.f && fabsf(v.w) <= 256.f;
+      byte = byte && v.x >= 0.f && v.y >= 0.f && v.z >= 0.f && v.w >= 0.f && v.x <= 255.f && v.y <= 255.f &&
+             v.z <= 255.f && v.w <= 255.f;
       nrm = __builtin_fmaf(v.x, v.x, __builtin_fmaf(v.y, v.y, __builtin_fmaf(v.z, v.z, __builtin_fmaf(v.w, v.w, nrm))));
     }
   }
@@ -208,9 +211,11 @@ __global__ __launch_bounds__(256) void k_exact_check(const float* __restrict__ X
   const bool row_int = ((nonint >> (threadIdx.x & 48)) & 0xFFFFull) == 0ull;
   if (row < n && gl == 0) pnorm[row] = row_int ? nrm : -nrm;
   const bool ok32 = integral && !(nrm > 4194304.0f);
-  const bool bad32 = __any(!ok32), bad16 = __any(!(ok32 && small));
-  if ((threadIdx.x & 63) == 0 && (bad32 || bad16))
-    atomicAnd(flags, ~((bad32 ? EXACT_FP32 : 0u) | EXACT_BF16));
+  const bool bad32 = __any(!ok32), bad16 = __any(!(ok32 && small)), bad8 = __any(!(integral && byte));
+  const unsigned int clear = (bad32 ? EXACT_FP32 : 0u) | (bad16 ? EXACT_BF16 : 0u) | (bad8 ? EXACT_U8 : 0u);
+  // a wave writes only bits that are still set, so the atomics stay few
+  if ((threadIdx.x & 63) == 0 && clear != 0u && (__atomic_load_n(flags, __ATOMIC_RELAXED) & clear) != 0u)
+    atomicAnd(flags, ~clear);
 }
 
 // One leaf: members perm[off .. off+m), rows written to ids/dist (already
@@ -847,16 +852,43 @@ hipError_t launch_leaf_kc(const LeafArgs& a, hipStream_t s) {
 
 }  // namespace
 
+// X as bytes (each value clamped to [0, 255]): sixteen values per thread,
+// four 16-byte loads and one 16-byte store; the last thread of a ragged end
+// goes four values at a time.
+__global__ __launch_bounds__(256) void k_byte_copy(const float* __restrict__ X, int64_t count, uint8_t* __restrict__ x8) {
+  const int64_t e0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
+  if (e0 >= count) return;
+  auto pack = [](float4 v) -> uint32_t {
+    const uint32_t b0 = (uint32_t)fminf(fmaxf(v.x, 0.f), 255.f), b1 = (uint32_t)fminf(fmaxf(v.y, 0.f), 255.f);
+    const uint32_t b2 = (uint32_t)fminf(fmaxf(v.z, 0.f), 255.f), b3 = (uint32_t)fminf(fmaxf(v.w, 0.f), 255.f);
+    return b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
+  };
+  const float4* xv = (const float4*)(X + e0);
+  if (e0 + 16 <= count) {
+    const float4 v0 = xv[0], v1 = xv[1], v2 = xv[2], v3 = xv[3];
+    *(uint4*)(x8 + e0) = make_uint4(pack(v0), pack(v1), pack(v2), pack(v3));
+  } else {
+    for (int64_t e = e0; e < count; e += 4) *(uint32_t*)(x8 + e) = pack(*(const float4*)(X + e));
+  }
+}
+
+hipError_t launch_data_check(const float* X, int64_t n, int d, uint32_t* flags, float* pnorm, uint8_t* x8,
+                             hipStream_t s) {
+  hipError_t e = launch_fill_u32(flags, EXACT_FP32 | EXACT_BF16 | EXACT_U8, 1, s);
+  if (e != hipSuccess || n <= 0) return e;
+  hipLaunchKernelGGL(k_exact_check, dim3((unsigned)((n * 16 + 255) / 256)), dim3(256), 0, s, X, n, d, flags, pnorm);
+  if ((e = hipGetLastError()) != hipSuccess || !x8) return e;
+  const int64_t count = n * (int64_t)d;
+  hipLaunchKernelGGL(k_byte_copy, dim3((unsigned)((count / 16 + 256) / 256)), dim3(256), 0, s, X, count, x8);
+  return hipGetLastError();
+}
+
 hipError_t launch_leaf(const LeafArgs& a, hipStream_t s) {
   hipError_t e;
   if (a.prepare_only) return a.precision == KNNG_BF16 ? launch_leaf_kc<true>(a, s) : launch_leaf_kc<false>(a, s);
   if ((e = launch_fill_u32((uint32_t*)&a.diag->fallback_count, 0u, 2, s)) != hipSuccess) return e;
-  if ((e = launch_fill_u32(&a.diag->exact_flags, EXACT_FP32 | EXACT_BF16, 1, s)) != hipSuccess) return e;
-  if (a.n > 0) {
-    hipLaunchKernelGGL(k_exact_check, dim3((unsigned)((a.n * 16 + 255) / 256)), dim3(256), 0, s, a.X, a.n, a.d,
-                       &a.diag->exact_flags, a.pnorm);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
+  if (!a.data_checked && (e = launch_data_check(a.X, a.n, a.d, &a.diag->exact_flags, a.pnorm, nullptr, s)) != hipSuccess)
+    return e;
   e = a.precision == KNNG_BF16 ? launch_leaf_kc<true>(a, s) : launch_leaf_kc<false>(a, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_leaf_exact, dim3(1024), dim3(256), 0, s, a);

@@ -378,6 +378,28 @@ def test_build_sift_small_bit_exact(dev):
     assert np.array_equal(gd[v].astype(np.float64), od[v])
 
 
+@pytest.mark.parametrize("split", [K.SPLIT_RP, K.SPLIT_PCA], ids=["rp", "pca"])
+def test_build_byte_copy_matches_standalone_stages(dev, split):
+    """On data whose values are all 0..255 the build's divide and propagation
+    read the one-byte copy of X; the standalone entry points read X itself.
+    The same values in the same arithmetic: the two must agree bit for bit."""
+    say("build byte copy vs standalone stages", split)
+    n, d, k, T = 20_000, 128, 10, 2
+    X = datagen.sift_like(n, d, 40, 83)
+    assert X.min() >= 0 and X.max() <= 255 and np.array_equal(X, np.rint(X))
+    kp, _ = _params(n, d, k, T=T, leaf_max=512, rounds=1, seed=84, split=split)
+    X_t = torch.from_numpy(X).to(dev)
+    bi, bd = K.knn_graph(X_t, kp)
+    Li, Ld = _lists_from_gpu(kp, X_t, dev, T)
+    si = torch.empty((n, k), dtype=torch.int32, device=dev)
+    sd = torch.empty((n, k), dtype=torch.float32, device=dev)
+    K.merge(kp, T, Li, Ld, si, sd)
+    ws = K.alloc_workspace(kp, K.OP_PROPAGATE, dev)
+    K.propagate(kp, X_t, si, sd, 1, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(bi, si) and torch.equal(bd, sd)
+
+
 def test_build_single_leaf_is_exact(dev):
     say("build single leaf")
     n, d, k = 1500, 24, 9
