@@ -116,7 +116,65 @@ __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
   //    (NCH float4 chunks per lane; NCH == 0 reads it from memory each time)
   const int g = lane >> 4, gl = lane & 15;
   const float* xp = a.X + (size_t)p * d;
-  if constexpr (NCH > 0) {
+  // Byte rows (every value of X an integer in 0..255, d <= 256 and a
+  // multiple of 8): every partial sum of a squared distance is an integer
+  // below 2^24, so any summation order gives dist2_g16's value exactly.  A
+  // lane then holds 8 consecutive values of p (block gl, and gl + 16 when
+  // d > 128) and reads one 8-byte piece of each candidate row: eight rows per
+  // lane group are in flight.
+  const bool u8 = a.X8 && (a.diag->exact_flags & EXACT_U8) != 0u && (d & 7) == 0 && d <= 256;   // uniform
+  if (u8) {
+    constexpr int R8 = 8;
+    const int nb = d >> 3;
+    float xq[2][8];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int blk = gl + 16 * b;
+      uint2 v = make_uint2(0u, 0u);
+      if (blk < nb) v = *(const uint2*)(a.X8 + (size_t)p * d + 8 * blk);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        xq[b][e] = (float)((v.x >> (8 * e)) & 0xFFu);
+        xq[b][4 + e] = (float)((v.y >> (8 * e)) & 0xFFu);
+      }
+    }
+    const bool two = nb > 16;   // uniform: a second block per lane
+    for (int base = 0; base < U; base += 4 * R8) {
+      // every lane loads (lanes past the row read block 0 and drop the sum
+      // afterwards), so no branch sits between the loads and their use
+      uint2 wr[R8][2];
+#pragma unroll
+      for (int j = 0; j < R8; ++j) {
+        const int ci = base + g + 4 * j;
+        const uint32_t o = ci < U ? cand_s[w][ci] : (uint32_t)p;
+        const uint8_t* yr = a.X8 + (size_t)o * d;
+        wr[j][0] = *(const uint2*)(yr + 8 * (gl < nb ? gl : 0));
+        wr[j][1] = two ? *(const uint2*)(yr + 8 * (gl + 16 < nb ? gl + 16 : 0)) : make_uint2(0u, 0u);
+      }
+#pragma unroll
+      for (int j = 0; j < R8; ++j) {
+        float part[2] = {0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          if (b == 1 && !two) break;   // uniform
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float y0 = (float)((wr[j][b].x >> (8 * e)) & 0xFFu), y1 = (float)((wr[j][b].y >> (8 * e)) & 0xFFu);
+            const float e0 = xq[b][e] - y0, e1 = xq[b][4 + e] - y1;
+            part[b] = __builtin_fmaf(e0, e0, part[b]);
+            part[b] = __builtin_fmaf(e1, e1, part[b]);
+          }
+        }
+        float acc = (gl < nb ? part[0] : 0.f) + (two && gl + 16 < nb ? part[1] : 0.f);
+        acc += __shfl_xor(acc, 8, 16);
+        acc += __shfl_xor(acc, 4, 16);
+        acc += __shfl_xor(acc, 2, 16);
+        acc += __shfl_xor(acc, 1, 16);
+        const int ci = base + g + 4 * j;
+        if (gl == 0 && ci < U) cd_s[w][ci] = acc;
+      }
+    }
+  } else if constexpr (NCH > 0) {
     float4 xr[NCH];
 #pragma unroll
     for (int i = 0; i < NCH; ++i) {

@@ -472,7 +472,8 @@ int leaf_batched(const knng_params& p, const Batch& B, const char* blob_dev, con
 }
 
 int prop_core(const knng_params& p, const float* X, uint32_t* ids, float* dist, int rounds, char* ws, DiagDev* diag,
-              const uint32_t* order, hipStream_t s, const std::function<hipError_t(int)>& after_round = nullptr) {
+              const uint32_t* order, hipStream_t s, const std::function<hipError_t(int)>& after_round = nullptr,
+              const uint8_t* x8 = nullptr) {
   PropLayout L = prop_layout(p);
   size_t nk = (size_t)p.n * p.k;
   uint32_t* tids = (uint32_t*)(ws + L.tmp_ids);
@@ -495,6 +496,7 @@ int prop_core(const knng_params& p, const float* X, uint32_t* ids, float* dist, 
     a.bucket = (uint32_t*)(ws + L.bucket);
     a.order = order;
     a.diag = diag;
+    a.X8 = x8;
     HIP_TRY(launch_propagate_round(a, s));
     if (after_round && !(r == rounds - 1 && rounds % 2 == 1)) HIP_TRY(after_round(r));
   }
@@ -795,7 +797,7 @@ static int build_impl(const knng_params* p, const float* X, const float* S, int 
   HIP_TRY(launch_merge(p->n, p->k, p->T, lists_ids, lists_dist, ids, dist, s));
   HIP_TRY(mark(3));
   if (p->rounds > 0) {
-    st = prop_core(*p, X, ids, dist, p->rounds, sh, diag, perms, s, [&](int r) { return mark(4 + r); });
+    st = prop_core(*p, X, ids, dist, p->rounds, sh, diag, perms, s, [&](int r) { return mark(4 + r); }, x8);
     if (st) return st;
   }
   return KNNG_OK;

@@ -177,6 +177,7 @@ struct PropArgs {
   uint32_t* bucket;                       // (src, dist) pairs grouped by dst
   const uint32_t* order;                  // nullable: the order points are processed in
   DiagDev* diag;
+  const uint8_t* X8;                      // nullable: one-byte copy of X, scored from when diag->exact_flags has EXACT_U8
 };
 hipError_t launch_propagate_round(const PropArgs& a, hipStream_t s);
 
