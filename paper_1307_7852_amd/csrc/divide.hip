@@ -304,38 +304,45 @@ __global__ __launch_bounds__(DIV_THREADS) void k_part_scatter(DivideLevelArgs a)
   }
 }
 
-// Principal direction of a node sample by FP32 power iteration (Section 3.4
-// takes the principal direction of points sampled from the subset).  When the
-// sample fits (SAMPLE_LDS) it is copied to LDS once, with every load in
-// flight together, centred there, and each iteration reads it twice:
-// t = Y v (a thread per sample row; rows padded by one float so the threads'
-// column reads fall in distinct banks) and w = Y^T t (a thread per feature).
-// Otherwise the same two passes read the rows from global memory.
-// Principal direction of one node's sample with the whole centred sample in
-// LDS (d <= PCA_LDS_DMAX).  Rows are padded to d + 4 floats, so float4
-// reads of one column by consecutive rows fall in different banks.
-// t = Y v: a thread per sample row, float4 over the columns.  w = Y^T t: a
-// thread per (column quad, slab of rows); slab partials are added in slab
-// order.  The mean is formed the same way.  The sample, start vector,
-// iteration count and sign rule are those of k_pca_dirs.
+// Principal direction of one node's sample by FP32 power iteration (Section
+// 3.4 takes the principal direction of points sampled from the subset), with
+// the whole sample in LDS (d <= PCA_LDS_DMAX).  t = Y v: a thread per sample
+// row, float4 over the columns.  w = Y^T t: a thread per (column quad, slab
+// of rows); slab partials are added in slab order.  The mean is formed the
+// same way.  The sample, start vector, iteration count and sign rule are
+// those of k_pca_dirs.
+// U8 = false: the sample is stored as floats, rows padded to d + 4 floats
+// (float4 reads of one column by consecutive rows fall in different banks),
+// and centred in place.  U8 = true (every value of X an integer in 0..255):
+// the rows are kept as bytes, padded to d + 4 bytes, and centred as they are
+// read; (float)byte - mean is the value the float form stores, so the
+// direction is the same bit for bit, and the quarter-size stage lets four
+// nodes share a CU.  Both forms are launched; each returns at once unless the
+// data check chose it.  Workgroups stride over the level's segments.
 constexpr int PCA_LDS_DMAX = 136;   // 256 (d + 4) + 2d + 256 + 1024 floats fit 150 KB
 
+template <bool U8>
 __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
+  const bool u8 = a.X8 && (*a.flags & EXACT_U8) != 0u;   // uniform
+  if (u8 != U8) return;
   extern __shared__ float smem[];
   const int d = a.d;
-  const int ld = d + 4;
+  const int ld = d + 4;                        // row stride: floats (U8: bytes)
   const int cw = d >> 2;                       // column quads
   const int G = DIV_THREADS / cw;              // row slabs
-  float* Y = smem;                             // 256 x ld
-  float* v = Y + 256 * ld;                     // d
+  float* Y = smem;                             // 256 x ld floats
+  uint8_t* Yb = reinterpret_cast<uint8_t*>(smem);   // 256 x ld bytes
+  float* v = U8 ? smem + 64 * ld : Y + 256 * ld;    // d
   float* mu = v + d;                           // d
   float* tt = mu + d;                          // 256
   float4* part = (float4*)(tt + 256);          // G x cw
   __shared__ uint32_t rows[256];
   __shared__ float red[DIV_THREADS / 64];
   __shared__ int redi[DIV_THREADS / 64];
-  const SegDesc sd = a.segs[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int q = tid % cw, g = tid / cw;
+  for (uint32_t seg = blockIdx.x; seg < a.n_segs; seg += gridDim.x) {
+  const SegDesc sd = a.segs[seg];
   const uint32_t m = sd.m;
   const uint32_t s = m < 256 ? m : 256;
   uint32_t wd = m / s;
@@ -346,14 +353,11 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
   }
   for (int j = tid; j < d; j += DIV_THREADS) v[j] = rp_entry(a.seed, sd.t, sd.v, (uint32_t)j);
   __syncthreads();
-  // raw sample -> LDS, 8 loads in flight per thread (from the one-byte
-  // copy when it holds X)
+  // raw sample -> LDS, 8 loads in flight per thread
   {
     const int tot = (int)s * cw;
-    const bool u8 = a.X8 && (*a.flags & EXACT_U8) != 0u;   // uniform
     for (int e0 = tid; e0 < tot; e0 += DIV_THREADS * 8) {
-      float4 buf[8];
-      if (u8) {
+      if constexpr (U8) {
         uint32_t wb[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -361,31 +365,50 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
           wb[u] = e < tot ? ((const uint32_t*)(a.X8 + (size_t)rows[e / cw] * d))[e % cw] : 0u;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) buf[u] = bytes4(wb[u]);
+        for (int u = 0; u < 8; ++u) {
+          int e = e0 + u * DIV_THREADS;
+          if (e < tot) *(uint32_t*)(Yb + (e / cw) * ld + 4 * (e % cw)) = wb[u];
+        }
       } else {
+        float4 buf[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           int e = e0 + u * DIV_THREADS;
           buf[u] = e < tot ? ((const float4*)(a.X + (size_t)rows[e / cw] * d))[e % cw] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
-      }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        int e = e0 + u * DIV_THREADS;
-        if (e < tot) *(float4*)(Y + (e / cw) * ld + 4 * (e % cw)) = buf[u];
+        for (int u = 0; u < 8; ++u) {
+          int e = e0 + u * DIV_THREADS;
+          if (e < tot) *(float4*)(Y + (e / cw) * ld + 4 * (e % cw)) = buf[u];
+        }
       }
     }
   }
   __syncthreads();
-  const int q = tid % cw, g = tid / cw;
+  bool centred = false;
+  // column quad qq of sample row i, centred once the mean is known
+  auto yq = [&](uint32_t i, int qq) -> float4 {
+    if constexpr (U8) {
+      const uint32_t b = *(const uint32_t*)(Yb + i * ld + 4 * qq);
+      float4 y = make_float4((float)(b & 0xFFu), (float)((b >> 8) & 0xFFu), (float)((b >> 16) & 0xFFu), (float)(b >> 24));
+      if (centred) {
+        const float4 m4 = *(const float4*)(mu + 4 * qq);
+        y.x -= m4.x; y.y -= m4.y; y.z -= m4.z; y.w -= m4.w;
+      }
+      return y;
+    } else {
+      return *(const float4*)(Y + i * ld + 4 * qq);
+    }
+  };
   const uint32_t rps = (s + G - 1) / G;        // rows per slab
   // column sums over a slab of rows, weighted by wt[i] (or 1), into part[g][q]
   auto slab_sums = [&](const float* wt) {
     if (g < G) {
       float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
       const uint32_t i0 = g * rps, i1 = min(s, i0 + rps);
+#pragma unroll 8
       for (uint32_t i = i0; i < i1; ++i) {
-        const float4 y = *(const float4*)(Y + i * ld + 4 * q);
+        const float4 y = yq(i, q);
         const float c = wt ? wt[i] : 1.f;
         acc.x = __builtin_fmaf(y.x, c, acc.x);
         acc.y = __builtin_fmaf(y.y, c, acc.y);
@@ -424,13 +447,16 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
     mu[4 * tid + 3] = t4.w * is;
   }
   __syncthreads();
-  for (int e = tid; e < (int)s * cw; e += DIV_THREADS) {
-    float4* yr = (float4*)(Y + (e / cw) * ld + 4 * (e % cw));
-    const float4 m4 = *(const float4*)(mu + 4 * (e % cw));
-    float4 y = *yr;
-    y.x -= m4.x; y.y -= m4.y; y.z -= m4.z; y.w -= m4.w;
-    *yr = y;
+  if constexpr (!U8) {
+    for (int e = tid; e < (int)s * cw; e += DIV_THREADS) {
+      float4* yr = (float4*)(Y + (e / cw) * ld + 4 * (e % cw));
+      const float4 m4 = *(const float4*)(mu + 4 * (e % cw));
+      float4 y = *yr;
+      y.x -= m4.x; y.y -= m4.y; y.z -= m4.z; y.w -= m4.w;
+      *yr = y;
+    }
   }
+  centred = true;
   // normalise the start vector
   float nn = 0.f;
   for (int j = tid; j < d; j += DIV_THREADS) nn += v[j] * v[j];
@@ -443,9 +469,9 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
   for (int itr = 0; itr < a.pca_iters; ++itr) {
     if (tid < (int)s) {   // t = Y v
       float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-      const float* yr = Y + tid * ld;
+#pragma unroll 8
       for (int c = 0; c < cw; ++c) {
-        const float4 y = *(const float4*)(yr + 4 * c);
+        const float4 y = yq(tid, c);
         const float4 vv = *(const float4*)(v + 4 * c);
         acc.x = __builtin_fmaf(y.x, vv.x, acc.x);
         acc.y = __builtin_fmaf(y.y, vv.y, acc.y);
@@ -488,6 +514,8 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
     if (red[i] > best || (red[i] == best && redi[i] < bj)) { best = red[i]; bj = redi[i]; }
   const float sg = v[bj] < 0.f ? -1.f : 1.f;
   for (int j = tid; j < d; j += DIV_THREADS) a.pca_dirs[(size_t)sd.dir_index * d + j] = sg * v[j];
+  __syncthreads();   // the next segment overwrites the stage, v and red
+  }
 }
 
 // Principal direction for d > PCA_LDS_DMAX: the centred sample is read from
@@ -631,14 +659,21 @@ hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s) {
     size_t base = (size_t)(2 * a.d + 256) * sizeof(float);
     if (a.d <= PCA_LDS_DMAX) {
       const int cw = a.d / 4, G = DIV_THREADS / cw;
-      size_t shm = ((size_t)256 * (a.d + 4) + 2 * (size_t)a.d + 256 + (size_t)G * cw * 4) * sizeof(float);
+      const size_t tail = (2 * (size_t)a.d + 256 + (size_t)G * cw * 4) * sizeof(float);
+      const size_t shm = (size_t)256 * (a.d + 4) * sizeof(float) + tail;
+      const size_t shm8 = (size_t)256 * (a.d + 4) + tail;   // 256 (d + 4) is a multiple of 16
       static bool attr = false;
       if (!attr) {
-        e = hipFuncSetAttribute((const void*)k_pca_lds, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        e = hipFuncSetAttribute((const void*)k_pca_lds<false>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
         if (e != hipSuccess) return e;
         attr = true;
       }
-      hipLaunchKernelGGL(k_pca_lds, dim3(a.n_segs), dim3(DIV_THREADS), shm, s, a);
+      // one workgroup per CU at the float stage's size; the byte stage fits four
+      const unsigned cus = (unsigned)cu_count();
+      hipLaunchKernelGGL(k_pca_lds<false>, dim3(std::min<unsigned>(a.n_segs, cus)), dim3(DIV_THREADS), shm, s, a);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if (a.X8)
+        hipLaunchKernelGGL(k_pca_lds<true>, dim3(std::min<unsigned>(a.n_segs, 4 * cus)), dim3(DIV_THREADS), shm8, s, a);
     } else {
       hipLaunchKernelGGL(k_pca_dirs, dim3(a.n_segs), dim3(DIV_THREADS), base, s, a);
     }

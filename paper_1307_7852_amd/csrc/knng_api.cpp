@@ -338,17 +338,6 @@ hipError_t zero_diag(void* diag, hipStream_t s) {
   return launch_fill_u32((uint32_t*)diag, 0u, sizeof(DiagDev) / 4, s);
 }
 
-int cu_count() {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-      cus = v;
-    else
-      cus = 256;
-  }
-  return cus;
-}
 
 // ------------------------------------------------------------------ stage cores
 // Runs every level of a batch of divisions with the batch's plan resident at
@@ -512,6 +501,18 @@ int prop_core(const knng_params& p, const float* X, uint32_t* ids, float* dist, 
 
 // ================================================================== planner
 namespace knng {
+
+int cu_count() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+    else
+      cus = 256;
+  }
+  return cus;
+}
 
 int64_t leaf_cap(const knng_params& p, int t) {
   if (p.leaf_cap_cycle == 0) return p.leaf_max;

@@ -135,6 +135,8 @@ struct DivideLevelArgs {
   const uint32_t* flags;
 };
 hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s);
+// compute units of the current device (cached after the first call)
+int cu_count();
 
 struct LeafArgs {
   const float* X; int64_t n; int d; int k; int kp; int precision;
