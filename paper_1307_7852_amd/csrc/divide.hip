@@ -7,6 +7,8 @@
 // the split is "key, then position in the segment".
 #include "knng_dev.h"
 
+#include <algorithm>
+
 namespace knng {
 
 namespace {
@@ -116,16 +118,25 @@ __device__ __forceinline__ float dot_seq(const float* __restrict__ x, const floa
       acc = acc + p3;
     }
   }
-  for (; c < c4; ++c) {
-    float4 u = xv[c];
-    float p0 = u.x * a[4 * c + 0];
-    acc = acc + p0;
-    float p1 = u.y * a[4 * c + 1];
-    acc = acc + p1;
-    float p2 = u.z * a[4 * c + 2];
-    acc = acc + p2;
-    float p3 = u.w * a[4 * c + 3];
-    acc = acc + p3;
+  if (c < c4) {   // the last 1..7 float4, all loads in flight together
+    const int r = c4 - c;
+    float4 u[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) u[k] = k < r ? xv[c + k] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k < r) {
+        const float* ak = a + 4 * (c + k);
+        float p0 = u[k].x * ak[0];
+        acc = acc + p0;
+        float p1 = u[k].y * ak[1];
+        acc = acc + p1;
+        float p2 = u[k].z * ak[2];
+        acc = acc + p2;
+        float p3 = u[k].w * ak[3];
+        acc = acc + p3;
+      }
+    }
   }
   return acc;
 }
@@ -668,12 +679,17 @@ hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s) {
         if (e != hipSuccess) return e;
         attr = true;
       }
-      // one workgroup per CU at the float stage's size; the byte stage fits four
+      // as many workgroups as the CUs' LDS holds at once (160 KB each, with
+      // the kernel's 1056 static bytes), at most eight per CU; they stride
+      // over the segments
       const unsigned cus = (unsigned)cu_count();
-      hipLaunchKernelGGL(k_pca_lds<false>, dim3(std::min<unsigned>(a.n_segs, cus)), dim3(DIV_THREADS), shm, s, a);
+      auto grid = [&](size_t bytes) {
+        const size_t per_cu = std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / (bytes + 1056)));
+        return dim3((unsigned)std::min<size_t>(a.n_segs, per_cu * cus));
+      };
+      hipLaunchKernelGGL(k_pca_lds<false>, grid(shm), dim3(DIV_THREADS), shm, s, a);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      if (a.X8)
-        hipLaunchKernelGGL(k_pca_lds<true>, dim3(std::min<unsigned>(a.n_segs, 4 * cus)), dim3(DIV_THREADS), shm8, s, a);
+      if (a.X8) hipLaunchKernelGGL(k_pca_lds<true>, grid(shm8), dim3(DIV_THREADS), shm8, s, a);
     } else {
       hipLaunchKernelGGL(k_pca_dirs, dim3(a.n_segs), dim3(DIV_THREADS), base, s, a);
     }
