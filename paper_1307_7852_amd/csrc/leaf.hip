@@ -305,8 +305,9 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
       }
       S.nrm[i] = v;
     }
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
     if (__any(bad) && lane == 0) S.flag = 0;
-    atomicMax(&S.max_n, __float_as_uint(mx));
+    if (lane == 0) atomicMax(&S.max_n, __float_as_uint(mx));
     __syncthreads();
   }
   const float eps_c = 2.0f * (float)(d + 4) * 5.9604645e-8f;   // 2 (d+4) 2^-24
@@ -386,8 +387,14 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     }
   };
 
+  // a pass followed by another over the same leaf stages that pass's first
+  // tile in its last step; bufbase keeps the double buffer's parity running
+  // across passes
+  int bufbase = 0;
+  bool staged = false;
   for (int qb = 0; qb < m; qb += C::QPB) {
     const bool first = qb == 0;
+    const bool follow = qb + C::QPB < m;      // another pass comes after this one
     const int qbase = qb + w * QPW;
     const bool wave_on = qbase < m;           // uniform per wave
     const int qpos = qbase + r32;             // this lane's query
@@ -438,23 +445,23 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
 #pragma unroll
     for (int j = 0; j < KP; ++j) Lk[j] = __uint_as_float(KEY_NONE);
     f32x16 acc0 = {0}, acc1 = {0};
-    {
+    if (!staged) {
       float4 rg[STAGE_F4];
       stage_load(0, rg);
-      stage_store(0, 0, rg, first && !pre_norms);
+      stage_store(0, bufbase, rg, first && !pre_norms);
     }
     __syncthreads();
     for (int st = 0; st < nsteps; ++st) {
-      const int buf = st & 1;
+      const int buf = (st + bufbase) & 1;
       const int c0 = (st / nchunk) * TILE, kci = st % nchunk;
       // the query chunk is loaded before the next tile's prefetch so that the
       // MFMAs wait only for the older loads and the prefetch stays in flight
       if (wave_on && nchunk > 1) qf.load(qrow, kci * KC, d, h, S.mu, qok);
       float4 rg[STAGE_F4];
-      // the last step re-stages its own tile into the idle buffer, so every
-      // step issues the same loads
+      // the last step stages the next pass's first tile, or re-stages its
+      // own, into the idle buffer, so every step issues the same loads
       const bool more = st + 1 < nsteps;
-      const int nxt = more ? st + 1 : st;
+      const int nxt = more ? st + 1 : follow ? 0 : st;
       stage_load(nxt, rg);
       if (wave_on) {
         if (kci == 0) {
@@ -529,6 +536,8 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
       stage_store(nxt, buf ^ 1, rg, first && more && !pre_norms);
       __syncthreads();
     }
+    staged = follow;
+    bufbase = (nsteps + bufbase) & 1;         // the buffer the last step filled
     if (!wave_on) continue;                   // no barrier below this point
     // ---- merge the two half-lists of each query: the KP smallest of both
     {
@@ -683,15 +692,19 @@ __global__ __launch_bounds__((Cfg<KP, W>::THREADS)) void k_leaf(LeafArgs a) {
   using Sh = LeafShared<KC, KP, BF16, W>;
   Sh& S = *reinterpret_cast<Sh*>(smem_raw);
   __shared__ uint32_t next;
+  // the index of the following work item is taken when a leaf starts, so
+  // the atomic's round trip overlaps the leaf's own loads
+  if (a.work && threadIdx.x == 0) next = atomicAdd(a.counter, 1u);
+  uint32_t following = 0;
   // single-division mode runs one pass of the loop for leaf blockIdx.x
   for (uint32_t pass = 0;; ++pass) {
     uint32_t idx;
     if (a.work) {
-      if (threadIdx.x == 0) next = atomicAdd(a.counter, 1u);
       __syncthreads();
       idx = next;
       __syncthreads();
       if (idx >= a.n_work) break;
+      if (threadIdx.x == 0) following = atomicAdd(a.counter, 1u);
     } else {
       if (pass > 0) break;
       idx = blockIdx.x;
@@ -713,6 +726,7 @@ __global__ __launch_bounds__((Cfg<KP, W>::THREADS)) void k_leaf(LeafArgs a) {
       m = (int)(a.leaf_off[idx + 1] - off);
     }
     leaf_body<KC, KP, BF16, W>(a, S, perm, ids_out, dist_out, off, m, idx);
+    if (a.work && threadIdx.x == 0) next = following;
     __syncthreads();
   }
 }
