@@ -378,13 +378,17 @@ def test_build_sift_small_bit_exact(dev):
     assert np.array_equal(gd[v].astype(np.float64), od[v])
 
 
-@pytest.mark.parametrize("split", [K.SPLIT_RP, K.SPLIT_PCA], ids=["rp", "pca"])
-def test_build_byte_copy_matches_standalone_stages(dev, split):
+@pytest.mark.parametrize("split,d", [(K.SPLIT_RP, 128), (K.SPLIT_PCA, 128), (K.SPLIT_PCA, 200), (K.SPLIT_RP, 36)],
+                         ids=["rp-d128", "pca-d128", "pca-d200", "rp-d36"])
+def test_build_byte_copy_matches_standalone_stages(dev, split, d):
     """On data whose values are all 0..255 the build's divide and propagation
     read the one-byte copy of X; the standalone entry points read X itself.
-    The same values in the same arithmetic: the two must agree bit for bit."""
-    say("build byte copy vs standalone stages", split)
-    n, d, k, T = 20_000, 128, 10, 2
+    The same values in the same arithmetic: the two must agree bit for bit.
+    d = 128: 16-byte row loads, one 8-byte block per lane in propagation;
+    d = 200: 4-byte row loads, two blocks per lane; d = 36: propagation keeps
+    the float rows (d is not a multiple of 8)."""
+    say("build byte copy vs standalone stages", split, d)
+    n, k, T = 20_000, 10, 2
     X = datagen.sift_like(n, d, 40, 83)
     assert X.min() >= 0 and X.max() <= 255 and np.array_equal(X, np.rint(X))
     kp, _ = _params(n, d, k, T=T, leaf_max=512, rounds=1, seed=84, split=split)
