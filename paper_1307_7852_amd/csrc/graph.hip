@@ -122,13 +122,16 @@ __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
   // lane then holds 8 consecutive values of p (block gl, and gl + 16 when
   // d > 128) and reads one 8-byte piece of each candidate row: eight rows per
   // lane group are in flight.
-  const bool u8 = a.X8 && (a.diag->exact_flags & EXACT_U8) != 0u && (d & 7) == 0 && d <= 256;   // uniform
+  // NB 8-value blocks per lane: one up to d = 128 (NCH <= 2), two up to 256
+  constexpr int NB = NCH >= 3 ? 2 : 1;
+  const bool u8 = NCH >= 1 && NCH <= 4 && a.X8 && (a.diag->exact_flags & EXACT_U8) != 0u && (d & 7) == 0 &&
+                  d <= 128 * NB;   // uniform
   if (u8) {
     constexpr int R8 = 8;
     const int nb = d >> 3;
-    float xq[2][8];
+    float xq[NB][8];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < NB; ++b) {
       const int blk = gl + 16 * b;
       uint2 v = make_uint2(0u, 0u);
       if (blk < nb) v = *(const uint2*)(a.X8 + (size_t)p * d + 8 * blk);
@@ -138,34 +141,36 @@ __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
         xq[b][4 + e] = (float)((v.y >> (8 * e)) & 0xFFu);
       }
     }
-    const bool two = nb > 16;   // uniform: a second block per lane
     for (int base = 0; base < U; base += 4 * R8) {
       // every lane loads (lanes past the row read block 0 and drop the sum
       // afterwards), so no branch sits between the loads and their use
-      uint2 wr[R8][2];
+      uint2 wr[R8][NB];
 #pragma unroll
       for (int j = 0; j < R8; ++j) {
         const int ci = base + g + 4 * j;
         const uint32_t o = ci < U ? cand_s[w][ci] : (uint32_t)p;
         const uint8_t* yr = a.X8 + (size_t)o * d;
-        wr[j][0] = *(const uint2*)(yr + 8 * (gl < nb ? gl : 0));
-        wr[j][1] = two ? *(const uint2*)(yr + 8 * (gl + 16 < nb ? gl + 16 : 0)) : make_uint2(0u, 0u);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int blk = gl + 16 * b;
+          wr[j][b] = *(const uint2*)(yr + 8 * (blk < nb ? blk : 0));
+        }
       }
 #pragma unroll
       for (int j = 0; j < R8; ++j) {
-        float part[2] = {0.f, 0.f};
+        float acc = 0.f;
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          if (b == 1 && !two) break;   // uniform
+        for (int b = 0; b < NB; ++b) {
+          float part = 0.f;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const float y0 = (float)((wr[j][b].x >> (8 * e)) & 0xFFu), y1 = (float)((wr[j][b].y >> (8 * e)) & 0xFFu);
             const float e0 = xq[b][e] - y0, e1 = xq[b][4 + e] - y1;
-            part[b] = __builtin_fmaf(e0, e0, part[b]);
-            part[b] = __builtin_fmaf(e1, e1, part[b]);
+            part = __builtin_fmaf(e0, e0, part);
+            part = __builtin_fmaf(e1, e1, part);
           }
+          acc += gl + 16 * b < nb ? part : 0.f;
         }
-        float acc = (gl < nb ? part[0] : 0.f) + (two && gl + 16 < nb ? part[1] : 0.f);
         acc += __shfl_xor(acc, 8, 16);
         acc += __shfl_xor(acc, 4, 16);
         acc += __shfl_xor(acc, 2, 16);
