@@ -231,7 +231,6 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
   const int d = a.d, k = a.k;
   const uint32_t L = key;
   if (m <= 0) return;
-  if (tid == 0) atomicAdd(&a.diag->leaf_rows, (unsigned long long)m);
   if (m > KNNG_MAX_LEAF) {   // every row goes to the exact kernel
     for (int i = tid; i < m; i += C::THREADS) {
       unsigned long long slot = atomicAdd(&a.diag->fallback_count, 1ull);
@@ -696,6 +695,7 @@ __global__ __launch_bounds__((Cfg<KP, W>::THREADS)) void k_leaf(LeafArgs a) {
   // the atomic's round trip overlaps the leaf's own loads
   if (a.work && threadIdx.x == 0) next = atomicAdd(a.counter, 1u);
   uint32_t following = 0;
+  unsigned long long rows = 0;   // members of this workgroup's leaves, added to the diagnostics once
   // single-division mode runs one pass of the loop for leaf blockIdx.x
   for (uint32_t pass = 0;; ++pass) {
     uint32_t idx;
@@ -726,9 +726,11 @@ __global__ __launch_bounds__((Cfg<KP, W>::THREADS)) void k_leaf(LeafArgs a) {
       m = (int)(a.leaf_off[idx + 1] - off);
     }
     leaf_body<KC, KP, BF16, W>(a, S, perm, ids_out, dist_out, off, m, idx);
+    if (m > 0) rows += (unsigned long long)m;
     if (a.work && threadIdx.x == 0) next = following;
     __syncthreads();
   }
+  if (threadIdx.x == 0 && rows) atomicAdd(&a.diag->leaf_rows, rows);
 }
 
 // Exact row: distances from one member to every other member of its leaf,
