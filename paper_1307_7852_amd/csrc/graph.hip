@@ -66,7 +66,7 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t nb) {
 }
 
 // Wave per point p:
-//   1. C_p = ids of N(q) for q in N(p), sorted, duplicates, p and N(p) dropped;
+//   1. C_p = ids of N(q) for q in N(p), duplicates, p and N(p) dropped (LDS hash);
 //   2. score every candidate with the canonical distance (16 lanes each);
 //   3. first k by (distance, id) of N(p) and C_p -> forward list;
 //   4. pairwise: propose p to every scored o when (D, p) beats o's frozen
@@ -75,6 +75,7 @@ template <int R1, int R2, int NCH>
 __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
   __shared__ uint32_t cand_s[4][64 * R1];
   __shared__ float cd_s[4][64 * R1];
+  __shared__ uint32_t htab[4][128 * R1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t vis = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * 4 + w;
   if (vis >= a.n) return;
@@ -82,32 +83,39 @@ __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
   const int k = a.k, d = a.d;
   uint32_t nb = lane < k ? a.ids_in[(size_t)p * k + lane] : KNNG_NONE;
   float nbd = lane < k ? a.dist_in[(size_t)p * k + lane] : __int_as_float(0x7F800000);
-  // 1. gather neighbours' lists
-  uint32_t c[R1];
-#pragma unroll
-  for (int r = 0; r < R1; ++r) {
-    int e = r * 64 + lane;
-    uint32_t o = KNNG_NONE;
-    int qi = e / k;
-    uint32_t q = __shfl(nb, qi < 64 ? qi : 0);
-    if (e < k * k && q != KNNG_NONE) o = a.ids_in[(size_t)q * k + (e % k)];
-    c[r] = o;
-  }
-  wave_bitonic<R1, 64 * R1, uint32_t>(c, lane);
+  // 1. C_p: the ids of N(q) for q in N(p), deduplicated through a per-wave
+  //    open-addressing table in LDS that first receives p and N(p), so those
+  //    are dropped too.  The candidates come out in table-race order; every
+  //    later step depends only on the set (keys are (distance, id)).
+  constexpr int TBL = 128 * R1;   // >= 2 (k^2) > k^2 + k + 1 entries
+  constexpr int LOG2_TBL = 7 + (R1 >= 2) + (R1 >= 4) + (R1 >= 8) + (R1 >= 16);
+  static_assert((1 << LOG2_TBL) == TBL, "table size");
+  uint32_t* ht = htab[w];
+  for (int i = lane; i < TBL; i += 64) ht[i] = KNNG_NONE;
+  wave_sync();
+  auto insert = [&](uint32_t id) -> bool {   // true: id was not in the table yet
+    uint32_t h = (id * 0x9E3779B1u) >> (32 - LOG2_TBL);
+    for (;;) {   // ends: the table always has empty slots
+      const uint32_t old = atomicCAS(&ht[h], KNNG_NONE, id);
+      if (old == KNNG_NONE) return true;
+      if (old == id) return false;
+      h = (h + 1) & (TBL - 1);
+    }
+  };
+  if (lane < k && nb != KNNG_NONE) insert(nb);
+  if (lane == 63) insert((uint32_t)p);
+  wave_sync();
   int U = 0;
 #pragma unroll
   for (int r = 0; r < R1; ++r) {
-    uint32_t pv = prev_elem<R1>(c, r, lane, KNNG_NONE);
-    uint32_t o = c[r];
-    bool u = o != KNNG_NONE && o != (uint32_t)p && o != pv;
-    // drop members of N(p); every lane runs every shuffle (a shuffle whose
-    // source lane is inactive does not deliver that lane's value)
-    for (int j = 0; j < k; ++j) {
-      uint32_t nj = (uint32_t)__shfl(nb, j);
-      u = u & (o != nj);
-    }
+    const int e = r * 64 + lane;
+    uint32_t o = KNNG_NONE;
+    const int qi = e / k;
+    const uint32_t q = __shfl(nb, qi < 64 ? qi : 0);
+    if (e < k * k && q != KNNG_NONE) o = a.ids_in[(size_t)q * k + (e % k)];
+    const bool u = o != KNNG_NONE && insert(o);
     int cnt;
-    int slot = U + wave_prefix_count(u, lane, &cnt);
+    const int slot = U + wave_prefix_count(u, lane, &cnt);
     if (u) cand_s[w][slot] = o;
     U += cnt;
   }
