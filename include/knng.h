@@ -175,7 +175,10 @@ int knng_propagate(const knng_params* p, const float* X, uint32_t* ids, float* d
 
 /* The whole method: p->T divisions (advanced level by level together),
  * leaf k-NN of every leaf of every division in one persistent launch
- * (largest leaves first), merge, p->rounds propagation rounds.
+ * (largest leaves first), merge, p->rounds propagation rounds.  One pass
+ * over X first records whether its values are integers (and whether all lie
+ * in 0..255, when the divisions and propagation read a one-byte copy of X
+ * kept in the workspace); the output is the same either way.
  * ids, dist (n x k) receive the graph.                                     */
 int knng_build(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
                void* stream);

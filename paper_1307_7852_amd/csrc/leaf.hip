@@ -20,9 +20,12 @@
 // candidate's lower bound (from the truncated key and the Gram's error bound)
 // is redone exactly by k_leaf_exact.
 //
-// Member norms, the exactness flag (all-integer data with small norms makes
-// the FP32 Gram exact) and the largest norm are gathered while the first
-// pass stages the tiles, so no separate sweep over the leaf is needed.
+// Member norms, the leaf's exactness flag (all-integer data with small norms
+// makes the FP32 Gram exact) and the largest norm come from the per-point
+// norms the data check wrote (k_exact_check: one pass over X per launch or
+// build); only a centred BF16 leaf forms its norms while its first pass
+// stages the tiles.  On integer data the keys carry the exact distance and
+// need no re-rank (see make_ikey).
 #include "knng_dev.h"
 
 #include <algorithm>
