@@ -351,6 +351,42 @@ __global__ __launch_bounds__(256) void k_prop_final(PropArgs a) {
     return;
   }
   uint64_t keep = lane < k ? pack_did(a.fwd_dist[(size_t)p * k + lane], a.fwd_ids[(size_t)p * k + lane]) : ~0ull;
+  // Only proposals below the forward list's k-th key can enter.  When those
+  // fit one register beside the list (the usual case), one 64-wide sort
+  // gives the answer.
+  if (b1 - b0 <= 64) {   // uniform
+    const uint32_t klo = __shfl((uint32_t)keep, k - 1), khi = __shfl((uint32_t)(keep >> 32), k - 1);
+    const uint64_t kth = ((uint64_t)khi << 32) | klo;
+    const uint32_t j = b0 + (uint32_t)lane;
+    const uint64_t key = j < b1 ? pack_did(__uint_as_float(a.bucket[2 * j + 1]), a.bucket[2 * j]) : ~0ull;
+    const bool in = key < kth;
+    int S;
+    const int slot = k + wave_prefix_count(in, lane, &S);
+    if (k + S <= 64) {   // uniform
+      kept[w][lane] = ~0ull;
+      wave_sync();
+      if (in) kept[w][slot] = key;
+      wave_sync();
+      uint64_t v[1];
+      v[0] = lane < k ? keep : kept[w][lane];
+      wave_bitonic<1, 64, uint64_t>(v, lane);
+      const uint64_t pv = prev_elem<1>(v, 0, lane, ~0ull);
+      const bool uniq = v[0] != ~0ull && key_id(pv) != key_id(v[0]);
+      int cnt;
+      const int out = wave_prefix_count(uniq, lane, &cnt);
+      wave_sync();
+      kept[w][lane] = ~0ull;
+      wave_sync();
+      if (uniq && out < k) kept[w][out] = v[0];
+      wave_sync();
+      if (lane < k) {
+        const uint64_t r = kept[w][lane];
+        a.ids_out[(size_t)p * k + lane] = key_id(r);
+        a.dist_out[(size_t)p * k + lane] = key_dist(r);
+      }
+      return;
+    }
+  }
   const uint32_t chunk = 64 * (R - 1);   // register 0 carries the kept list
   uint32_t pos = b0;
   do {
