@@ -18,8 +18,9 @@ template <int R>
 __global__ __launch_bounds__(256) void k_merge(int64_t n, int k, int n_lists, const uint32_t* __restrict__ ids_in,
                                                 const float* __restrict__ dist_in, uint32_t* __restrict__ ids_out,
                                                 float* __restrict__ dist_out) {
-  const int lane = threadIdx.x & 63;
-  const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  __shared__ uint64_t sk[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t p = (int64_t)blockIdx.x * 4 + w;
   if (p >= n) return;
   const int tot = n_lists * k;
   const size_t nk = (size_t)n * k;
@@ -34,6 +35,49 @@ __global__ __launch_bounds__(256) void k_merge(int64_t n, int k, int n_lists, co
       key = pack_did(dist_in[idx], ids_in[idx]);
     }
     v[r] = key;
+  }
+  if constexpr (R > 1) {
+    // The first list's largest key bounds the union's k-th: only keys below
+    // it (besides that list) can enter.  When those fit one register beside
+    // the first list (the usual case), one 64-wide sort replaces the wider one.
+    uint64_t mx = lane < k ? v[0] : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t lo = __shfl_xor((uint32_t)mx, o), hi = __shfl_xor((uint32_t)(mx >> 32), o);
+      const uint64_t x = ((uint64_t)hi << 32) | lo;
+      mx = x > mx ? x : mx;
+    }
+    int S = 0;
+    sk[w][lane] = ~0ull;
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int e = r * 64 + lane;
+      const bool in = e >= k && v[r] < mx;
+      int cnt;
+      const int slot = k + S + wave_prefix_count(in, lane, &cnt);
+      if (in && slot < 64) sk[w][slot] = v[r];
+      S += cnt;
+    }
+    wave_sync();
+    if (k + S <= 64) {   // uniform
+      uint64_t u[1];
+      u[0] = lane < k ? v[0] : sk[w][lane];
+      wave_bitonic<1, 64, uint64_t>(u, lane);
+      const uint64_t pv = prev_elem<1>(u, 0, lane, ~0ull);
+      const bool uniq = u[0] != ~0ull && key_id(pv) != key_id(u[0]);
+      int cnt;
+      const int slot = wave_prefix_count(uniq, lane, &cnt);
+      if (uniq && slot < k) {
+        ids_out[(size_t)p * k + slot] = key_id(u[0]);
+        dist_out[(size_t)p * k + slot] = key_dist(u[0]);
+      }
+      for (int s2 = cnt + lane; s2 < k; s2 += 64) {
+        ids_out[(size_t)p * k + s2] = KNNG_NONE;
+        dist_out[(size_t)p * k + s2] = __int_as_float(0x7F800000);
+      }
+      return;
+    }
   }
   wave_bitonic<R, 64 * R, uint64_t>(v, lane);
   int base = 0;
