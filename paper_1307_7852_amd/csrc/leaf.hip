@@ -40,6 +40,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int QPW = 32;            // queries per wave
 constexpr int TILE = 32;           // candidates per tile
+constexpr int TILE_BUFS = 4;       // tile buffers in LDS: staged two steps ahead, a barrier every second step
 constexpr int MU_MAX = 2048;       // BF16 path: d <= 2048
 constexpr uint32_t POS_MASK = 0x7FFu;          // position bits of a key (leaf <= 2048)
 constexpr uint32_t KEY_NONE = 0x7F7FFFFFu;     // FLT_MAX: above every key
@@ -143,7 +144,7 @@ struct LeafShared {
   using C = Cfg<KP, W>;
   uint32_t ids[KNNG_MAX_LEAF];
   float nrm[KNNG_MAX_LEAF];                 // member norms (centred BF16: of the rounded centred rows)
-  TileT<KC, BF16> tile[2];
+  TileT<KC, BF16> tile[TILE_BUFS];
   float mu[BF16 ? MU_MAX : 1];
   uint32_t max_n;                           // largest member norm (float bits)
   int flag;                                 // every value integral and every norm <= 2^22 (BF16: |value| <= 256)
@@ -389,9 +390,13 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     }
   };
 
-  // a pass followed by another over the same leaf stages that pass's first
-  // tile in its last step; bufbase keeps the double buffer's parity running
-  // across passes
+  // Tiles are staged two steps ahead into four LDS buffers with a barrier
+  // after every second step, so the waves of a SIMD may drift apart by a
+  // step (one's key insertion overlapping the other's MFMAs).  A store at
+  // step s goes to the buffer read at s + 2 (last read at s - 2), and the
+  // barrier between them orders both.  A pass followed by another over the
+  // same leaf stages that pass's first two tiles in its last two steps;
+  // bufbase keeps the buffer rotation running across passes.
   int bufbase = 0;
   bool staged = false;
   for (int qb = 0; qb < m; qb += C::QPB) {
@@ -448,22 +453,27 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     for (int j = 0; j < KP; ++j) Lk[j] = __uint_as_float(KEY_NONE);
     f32x16 acc0 = {0}, acc1 = {0};
     if (!staged) {
-      float4 rg[STAGE_F4];
-      stage_load(0, rg);
-      stage_store(0, bufbase, rg, first && !pre_norms);
+      for (int s0 = 0; s0 < 2 && s0 < nsteps; ++s0) {
+        float4 rg[STAGE_F4];
+        stage_load(s0, rg);
+        stage_store(s0, (s0 + bufbase) % TILE_BUFS, rg, first && !pre_norms);
+      }
     }
     __syncthreads();
     for (int st = 0; st < nsteps; ++st) {
-      const int buf = (st + bufbase) & 1;
+      const int buf = (st + bufbase) % TILE_BUFS;
       const int c0 = (st / nchunk) * TILE, kci = st % nchunk;
       // the query chunk is loaded before the next tile's prefetch so that the
       // MFMAs wait only for the older loads and the prefetch stays in flight
       if (wave_on && nchunk > 1) qf.load(qrow, kci * KC, d, h, S.mu, qok);
       float4 rg[STAGE_F4];
-      // the last step stages the next pass's first tile, or re-stages its
-      // own, into the idle buffer, so every step issues the same loads
-      const bool more = st + 1 < nsteps;
-      const int nxt = more ? st + 1 : follow ? 0 : st;
+      // step st stages step st + 2 of this pass, or of the next pass over
+      // the leaf, or else re-stages its own tile into a buffer nobody reads
+      // again, so every step issues the same loads
+      const int ahead = st + 2;
+      const bool more = ahead < nsteps;
+      const bool carry = !more && follow && nsteps >= 2;   // the next pass's step ahead - nsteps
+      const int nxt = more ? ahead : carry ? ahead - nsteps : st;
       stage_load(nxt, rg);
       if (wave_on) {
         if (kci == 0) {
@@ -535,11 +545,11 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
           }
         }
       }
-      stage_store(nxt, buf ^ 1, rg, first && more && !pre_norms);
-      __syncthreads();
+      stage_store(nxt, (ahead + bufbase) % TILE_BUFS, rg, first && more && !pre_norms);
+      if ((st & 1) || st + 1 == nsteps) __syncthreads();
     }
-    staged = follow;
-    bufbase = (nsteps + bufbase) & 1;         // the buffer the last step filled
+    staged = follow && nsteps >= 2;
+    bufbase = (nsteps + bufbase) % TILE_BUFS;   // the buffer of the next pass's step 0
     if (!wave_on) continue;                   // no barrier below this point
     // ---- merge the two half-lists of each query: the KP smallest of both
     {
