@@ -508,7 +508,8 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
           const bool diag = (c0 == qbase);   // uniform: the tile holding the wave's own queries
           const bool ragged = c0 + TILE > m;  // uniform: the last tile has padding rows
           // EXACT: integer keys; EDGE: the tile needs the self-pair or padding
-          // masks; KI: list entries kept (integer keys need only the k smallest)
+          // masks; KI: list entries kept (integer keys need only the k smallest:
+          // KP/2, 5KP/8, 3KP/4 or KP, the first that holds k)
           auto insert_tile = [&](auto exact_tag, auto edge_tag, auto len_tag) {
             constexpr bool EXACT = decltype(exact_tag)::value;
             constexpr bool EDGE = decltype(edge_tag)::value;
@@ -530,11 +531,14 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
           using F_ = std::false_type;
           using KFull = std::integral_constant<int, KP>;
           using KHalf = std::integral_constant<int, KP / 2>;
+          using K58 = std::integral_constant<int, KP / 2 + KP / 8>;
           using K3q = std::integral_constant<int, KP - KP / 4>;
           if (ikey) {
             const bool edge = diag || ragged;
             if (k <= KP / 2) {
               if (edge) insert_tile(T_{}, T_{}, KHalf{}); else insert_tile(T_{}, F_{}, KHalf{});
+            } else if (k <= KP / 2 + KP / 8) {
+              if (edge) insert_tile(T_{}, T_{}, K58{}); else insert_tile(T_{}, F_{}, K58{});
             } else if (k <= KP - KP / 4) {
               if (edge) insert_tile(T_{}, T_{}, K3q{}); else insert_tile(T_{}, F_{}, K3q{});
             } else {
