@@ -319,9 +319,9 @@ __global__ __launch_bounds__(DIV_THREADS) void k_part_scatter(DivideLevelArgs a)
 // 3.4 takes the principal direction of points sampled from the subset), with
 // the whole sample in LDS (d <= PCA_LDS_DMAX).  t = Y v: a thread per sample
 // row, float4 over the columns.  w = Y^T t: a thread per (column quad, slab
-// of rows); slab partials are added in slab order.  The mean is formed the
-// same way.  The sample, start vector, iteration count and sign rule are
-// those of k_pca_dirs.
+// of rows); slab partials are added in a fixed order (four chains).  The
+// mean is formed the same way.  The sample, start vector, iteration count
+// and sign rule are those of k_pca_dirs.
 // U8 = false: the sample is stored as floats, rows padded to d + 4 floats
 // (float4 reads of one column by consecutive rows fall in different banks),
 // and centred in place.  U8 = true (every value of X an integer in 0..255):
@@ -430,13 +430,26 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
     }
     __syncthreads();
   };
+  // slab partials of column quad qq summed in four interleaved chains (slab
+  // g into chain g mod 4), then (c0 + c1) + (c2 + c3): a fixed order whose
+  // dependent chain is a quarter as long (G reaches 64 at d = 16)
   auto col_total = [&](int qq) -> float4 {
-    float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int gg = 0; gg < G; ++gg) {
-      const float4 p4 = part[gg * cw + qq];
-      r.x += p4.x; r.y += p4.y; r.z += p4.z; r.w += p4.w;
+    float4 c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto add = [](float4& r, const float4 p4) { r.x += p4.x; r.y += p4.y; r.z += p4.z; r.w += p4.w; };
+    int gg = 0;
+    for (; gg + 4 <= G; gg += 4) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) add(c[j], part[(gg + j) * cw + qq]);
     }
-    return r;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (gg + j < G) add(c[j], part[(gg + j) * cw + qq]);
+    add(c[0], c[1]);
+    add(c[2], c[3]);
+    add(c[0], c[2]);
+    return c[0];
   };
   auto block_sum = [&](float x) -> float {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
