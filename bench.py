@@ -295,7 +295,12 @@ def main():
     # propagation: algorithmic bytes of the last round from its candidate count
     U = diag["prop_candidates"]
     nk = w.n * w.k
-    prop_bytes = (4.0 * w.k * w.k * w.n + 4.0 * w.d * (U + w.n) + 24.0 * nk + 16.0 * U)
+    # candidate rows are read from the one-byte copy when every value of X is
+    # an integer in 0..255 and d <= 256 is a multiple of 8 (the library's rule)
+    byte_rows = bool(np.all(X >= 0) and np.all(X <= 255) and np.array_equal(X, np.rint(X))
+                     and w.d % 8 == 0 and w.d <= 256)
+    row_bytes = w.d if byte_rows else 4.0 * w.d
+    prop_bytes = (4.0 * w.k * w.k * w.n + row_bytes * (U + w.n) + 24.0 * nk + 16.0 * U)
     prop_round_ms = prop_ms / max(1, rounds)
     prop_gbs = prop_bytes / (prop_round_ms * 1e-3) / 1e9 if rounds else 0.0
 
