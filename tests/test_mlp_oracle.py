@@ -126,3 +126,38 @@ def test_sample_pairs_definition():
         assert b in set(ids[i]) or (b == i and (ids[i] == 0xFFFFFFFF).any())
     assert np.array_equal(pr, M.sample_pairs(ids, n, k, 5, 7, 300, 200))
     assert not np.array_equal(pr, M.sample_pairs(ids, n, k, 5, 8, 300, 200))
+
+
+def test_forward_hand_worked():
+    """The network z = W2 relu(W1 (s x) + b1) + b2 on a case worked by hand:
+    s = 1/2, x = (4, 6, 2) -> s x = (2, 3, 1);
+    W1 (s x) + b1 = (2 - 3 + 0 + 2, 1 + 6 - 1 - 1, -2 + 0 + 3 - 2) = (1, 5, -1);
+    relu -> (1, 5, 0); W2 h + b2 = (1 + 10 + 0 + 0.25, -1 + 2.5 + 0 - 3)
+    = (11.25, -1.5).  The zero row gives h = relu(b1) = (2, 0, 0) and
+    z = (2 + 0.25, -2 - 3).  Dropping the scale, either bias or the ReLU,
+    or transposing W1, changes the answer."""
+    P = {"W1": np.array([[1.0, -1.0, 0.0], [0.5, 2.0, -1.0], [-1.0, 0.0, 3.0]]),
+         "b1": np.array([2.0, -1.0, -2.0]),
+         "W2": np.array([[1.0, 2.0, 5.0], [-1.0, 0.5, 7.0]]),
+         "b2": np.array([0.25, -3.0])}
+    X = np.array([[4.0, 6.0, 2.0], [0.0, 0.0, 0.0]])
+    z, (x, a1, h) = M.forward(P, X, 0.5)
+    assert np.array_equal(z, np.array([[11.25, -1.5], [2.25, -5.0]]))
+    assert np.array_equal(a1[0], np.array([1.0, 5.0, -1.0]))
+    assert np.array_equal(h[0], np.array([1.0, 5.0, 0.0]))
+
+
+def test_forward_bf16_operands_hand_worked():
+    """With bfloat16 operands (8 significant bits, ties to even): s x =
+    1 + 2^-8 lies halfway between 1 and 1 + 2^-7 and rounds to 1;
+    W1 = 1 + 3 2^-8 rounds up to 1 + 2^-6; the hidden value 1 + 2^-6 is
+    representable; W2 = 3 + 2^-7 lies halfway between 3 and 3 + 2^-6 and
+    rounds to 3 (even).  So z = (1 + 2^-6) 3 + 1/2 = 3.546875, while the
+    unrounded network gives a different value."""
+    P = {"W1": np.array([[1.0 + 3 * 2.0 ** -8]]), "b1": np.array([0.0]),
+         "W2": np.array([[3.0 + 2.0 ** -7]]), "b2": np.array([0.5])}
+    X = np.array([[2.0 + 2.0 ** -7]])
+    z, _ = M.forward(P, X, 0.5, rnd=M.bf16)
+    assert z[0, 0] == 3.546875
+    z64, _ = M.forward(P, X, 0.5)
+    assert z64[0, 0] == (1 + 2.0 ** -8) * (1 + 3 * 2.0 ** -8) * (3 + 2.0 ** -7) + 0.5
