@@ -578,21 +578,28 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
         // the two lanes of a query write alternate slots
         if (qok) {
           const uint32_t qid = S.ids[qpos];
+          // a saturated entry among the written ones (the list is ascending,
+          // so the last valid one is the largest) carries neither its true
+          // distance nor its (distance, id) order: the row is redone exactly.
+          // Rows of leaves with at most k members have padding at slot k - 1,
+          // so the check covers every written slot, not only the k-th.
+          bool sat = false;
 #pragma unroll
           for (int j = 0; j < KP; ++j) {
+            const uint32_t kk = __float_as_uint(Lk[j]);
+            const bool none = kk == KEY_NONE;
+            if (j < k) sat = sat || (!none && (kk >> 11) >= KEY_DSAT);
             if (j < k && (j & 1) == h) {
-              const uint32_t kk = __float_as_uint(Lk[j]);
-              const bool none = kk == KEY_NONE;
               ids_out[(size_t)qid * k + j] = none ? KNNG_NONE : S.ids[kk & POS_MASK];
               dist_out[(size_t)qid * k + j] = none ? INF : (float)(kk >> 11);
-              if (j == k - 1 && !none && (kk >> 11) >= KEY_DSAT) {   // saturated: order not exact
-                unsigned long long sl = atomicAdd(&a.diag->fallback_count, 1ull);
-                atomicAdd(&a.diag->leaf_fallback, 1ull);
-                if (sl < a.fallback_cap) {
-                  a.fallback[2 * sl] = L;
-                  a.fallback[2 * sl + 1] = (uint32_t)qpos;
-                }
-              }
+            }
+          }
+          if (sat && h == 0) {
+            unsigned long long sl = atomicAdd(&a.diag->fallback_count, 1ull);
+            atomicAdd(&a.diag->leaf_fallback, 1ull);
+            if (sl < a.fallback_cap) {
+              a.fallback[2 * sl] = L;
+              a.fallback[2 * sl + 1] = (uint32_t)qpos;
             }
           }
         }
