@@ -157,6 +157,20 @@ int knng_divide(const knng_params* p, int t, const float* X, const float* dir_ov
 int knng_leaf_knn(const knng_params* p, const float* X, const uint32_t* perm, const int64_t* leaf_off,
                   int64_t n_leaves, uint32_t* ids, float* dist, void* ws, size_t ws_bytes, void* stream);
 
+/* knng_leaf_knn for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): it
+ * takes no workspace and allocates nothing.  Its scratch (diagnostics,
+ * fallback rows, member norms) is one array inside the library of
+ * 12 bytes per point for KNNG_NOALLOC_MAX_N points (about 25 MB) per GPU,
+ * held until the process ends, so n is at most KNNG_NOALLOC_MAX_N (larger
+ * n: KNNG_EINVAL, nothing enqueued).
+ * Every call on one GPU shares that array: calls that overlap on a GPU
+ * (other threads, other streams) race and must be serialised by the caller.
+ * Arguments and results as knng_leaf_knn.                                   */
+#define KNNG_NOALLOC_MAX_N ((int64_t)1 << 21)
+int knng_leaf_knn_noalloc(const knng_params* p, const float* X, const uint32_t* perm, const int64_t* leaf_off,
+                          int64_t n_leaves, uint32_t* ids, float* dist, void* stream);
+
 /* Combination of base graphs (Section 3.1): per point, unite n_lists lists,
  * drop duplicate ids, keep the first k by (distance, id).
  *   ids_in, dist_in (n_lists x n x k); ids_out, dist_out (n x k), which must

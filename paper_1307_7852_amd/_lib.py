@@ -21,6 +21,7 @@ SPLIT_RP, SPLIT_PCA = 0, 1
 FP32, BF16 = 0, 1
 OP_DIVIDE, OP_LEAF, OP_MERGE, OP_PROPAGATE, OP_BUILD, OP_COLEAF = 0, 1, 2, 3, 4, 5
 MLP_HIDDEN, MLP_EMB = 256, 16
+NOALLOC_MAX_N = 1 << 21
 
 
 class _CParams(ctypes.Structure):
@@ -89,6 +90,7 @@ def _load():
                                   ctypes.POINTER(ctypes.c_int32)]),
         "knng_divide": (i32, [P, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
         "knng_leaf_knn": (i32, [P, vp, vp, vp, i64, vp, vp, vp, sz, vp]),
+        "knng_leaf_knn_noalloc": (i32, [P, vp, vp, vp, i64, vp, vp, vp]),
         "knng_merge": (i32, [P, i32, vp, vp, vp, vp, vp]),
         "knng_propagate": (i32, [P, vp, vp, vp, i32, vp, sz, vp]),
         "knng_build": (i32, [P, vp, vp, vp, vp, sz, vp]),
@@ -123,7 +125,7 @@ def _load():
 
 _lib = _load()
 EXPORTS = ["knng_status_str", "knng_last_error", "knng_workspace_bytes", "knng_tree_shape", "knng_divide",
-           "knng_leaf_knn", "knng_merge", "knng_propagate", "knng_build", "knng_read_diag", "knng_build_timed",
+           "knng_leaf_knn", "knng_leaf_knn_noalloc", "knng_merge", "knng_propagate", "knng_build", "knng_read_diag", "knng_build_timed",
            "knng_build_split", "knng_coleaf_rate", "knng_learned_choice", "knng_mlp_param_count", "knng_mlp_init", "knng_mlp_forward",
            "knng_mlp_workspace_bytes", "knng_mlp_grad", "knng_mlp_adam", "knng_mlp_sample_pairs", "knng_mlp_train",
            "knng_leaf_set_config", "knng_leaf_tune", "knng_graph_create", "knng_graph_launch", "knng_graph_destroy"]
@@ -180,6 +182,14 @@ def leaf_knn(p: Params, X, perm, leaf_off, n_leaves: int, ids, dist, ws, stream=
     cp = p.c()
     _check(_lib.knng_leaf_knn(ctypes.byref(cp), _ptr(X), _ptr(perm), _ptr(leaf_off), n_leaves, _ptr(ids), _ptr(dist),
                               _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def leaf_knn_noalloc(p: Params, X, perm, leaf_off, n_leaves: int, ids, dist, stream=None):
+    """knng_leaf_knn without a workspace (the library's own scratch array;
+    n <= NOALLOC_MAX_N; calls on one GPU must not overlap)."""
+    cp = p.c()
+    _check(_lib.knng_leaf_knn_noalloc(ctypes.byref(cp), _ptr(X), _ptr(perm), _ptr(leaf_off), n_leaves, _ptr(ids),
+                                      _ptr(dist), _stream(stream)))
 
 
 def merge(p: Params, n_lists: int, ids_in, dist_in, ids_out, dist_out, stream=None):

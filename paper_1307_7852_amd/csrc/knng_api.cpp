@@ -985,6 +985,59 @@ int knng_leaf_tune(const knng_params* p, const float* X, void* ws, size_t ws_byt
   return KNNG_OK;
 }
 
+// ------------------------------------------------------------------ allocation-free leaf k-NN
+// knng_leaf_knn's scratch (diagnostics, fallback list, work counter, member
+// norms) for up to KNNG_NOALLOC_MAX_N points lives in one device array of
+// the library, so callers that may not allocate device memory need no
+// workspace.  Host code never passes the array's name to a kernel: that
+// name is a host-side stand-in; its device address is taken once per device
+// with hipGetSymbolAddress and used everywhere instead.
+namespace {
+constexpr size_t NOALLOC_BYTES = ((sizeof(DiagDev) + 255) & ~(size_t)255) + (size_t)KNNG_NOALLOC_MAX_N * 8 + 256 +
+                                 (size_t)KNNG_NOALLOC_MAX_N * 4;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device ordinal -> address of that device's copy of `scratch`
+
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return KNNG_OK;
+  }
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return fail(KNNG_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+  g_scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return KNNG_OK;
+}
+}  // namespace
+
+int knng_leaf_knn_noalloc(const knng_params* p, const float* X, const uint32_t* perm, const int64_t* leaf_off,
+                          int64_t n_leaves, uint32_t* ids, float* dist, void* stream) {
+  int st = validate(p);
+  if (st) return st;
+  if (p->n > KNNG_NOALLOC_MAX_N)
+    return fail(KNNG_EINVAL, "knng_leaf_knn_noalloc handles at most %lld points (got n=%lld); use knng_leaf_knn",
+                (long long)KNNG_NOALLOC_MAX_N, (long long)p->n);
+  if (!X || !perm || !leaf_off || !ids || !dist) return fail(KNNG_EINVAL, "null array argument");
+  if (!aligned16(X)) return fail(KNNG_EINVAL, "X must be 16-byte aligned");
+  if (n_leaves < 1 || n_leaves > p->n) return fail(KNNG_EINVAL, "n_leaves=%lld out of [1, n]", (long long)n_leaves);
+  LeafLayout L = leaf_layout(*p, 1);
+  if (L.total > NOALLOC_BYTES) return fail(KNNG_EINVAL, "scratch layout exceeds the library's array");
+  void* sp = nullptr;
+  st = noalloc_scratch(&sp);
+  if (st) return st;
+  char* w = (char*)sp;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(zero_diag(w + L.diag, s));
+  return leaf_single(*p, X, perm, leaf_off, n_leaves, ids, dist, w, (DiagDev*)(w + L.diag), s);
+}
+
 struct KnngGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;

@@ -98,3 +98,16 @@ def test_tree_shape_matches_oracle_live(n, leaf_max, cyc, qlo, qhi, seed, t):
     assert off == O.leaf_offsets(po, t).tolist()
     assert n_int == sum(len(l) for l in levels)
     assert depth == len(levels)
+
+
+def test_noalloc_leaf_rejects_inputs_beyond_its_array():
+    """The allocation-free leaf entry point checks n against the size of its
+    scratch array before touching the GPU."""
+    lib = _lib.raw()
+    cp = _p(n=K.NOALLOC_MAX_N + 1, leaf_max=256).c()
+    r = lib.knng_leaf_knn_noalloc(ctypes.byref(cp), None, None, None, 1, None, None, None)
+    assert r == -1
+    assert b"at most" in lib.knng_last_error()
+    cp = _p(n=1000).c()
+    assert lib.knng_leaf_knn_noalloc(ctypes.byref(cp), None, None, None, 1, None, None, None) == -1
+    assert b"null" in lib.knng_last_error()
