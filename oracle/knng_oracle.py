@@ -35,10 +35,27 @@ Readings where the paper is silent (each listed in the design doc):
   R6  each child keeps its parent's relative order, the root order is 0..n-1;
   R7  a propagation round reads a frozen graph (Jacobi style) and, with
       pairwise updating, every evaluated pair (p, o) also proposes p to o;
-  R8  lists shorter than k are padded with (NONE, +inf).
+  R8  lists shorter than k are padded with (NONE, +inf);
+  R18 best-first propagation (Section 3.2): a point counts as visited when
+      its distance to p is evaluated; p's current neighbours are known and
+      seed the queue without using the budget; the queue pops by
+      (distance, id); a popped point's neighbours are evaluated in its list
+      order and the pass stops as soon as the budget is used up or the queue
+      is empty; like R7 every point reads the frozen graph;
+  R19 the effective rate r_m (Section 3.2) counts the per-division k-lists
+      (N~^m_p is the union of p's lists of divisions 1..m); divisions stop at
+      the first m with r_m < rate, compared exactly as
+      1000 * new_m < rate_permille * total_m;
+  R20 cosine distance (Definition 1 names it beside the Euclidean distance):
+      rows are scaled to unit length in float32 (sum of squares left to
+      right, each product and sum rounded, correctly rounded square root and
+      quotients; a zero row stays zero) and the Euclidean method runs on the
+      scaled rows, whose squared distance is 2 (1 - cos theta): it ranks like
+      the cosine distance 1 - cos theta.
 """
 from __future__ import annotations
 
+import heapq
 import math
 from dataclasses import dataclass
 
@@ -234,6 +251,34 @@ def divide(X: np.ndarray, p: Params, t: int, split: str = "rp", dirs: dict | Non
     return perm, leaf_offsets(p, t), used
 
 
+# ---------------------------------------------------------------- cosine metric (R20)
+def normalize_rows(X: np.ndarray) -> np.ndarray:
+    """Rows scaled to unit length in float32: s = sum over features, left to
+    right, of x_j * x_j (each product and each sum rounded to float32), then
+    x_j / sqrt(s) with the square root and every quotient correctly rounded.
+    A zero row stays zero."""
+    X = np.asarray(X, dtype=np.float32)
+    s = np.zeros(X.shape[0], dtype=np.float32)
+    for j in range(X.shape[1]):
+        s = (s + (X[:, j] * X[:, j]).astype(np.float32)).astype(np.float32)
+    nrm = np.sqrt(s).astype(np.float32)
+    out = np.zeros_like(X)
+    nz = nrm > 0
+    out[nz] = (X[nz] / nrm[nz, None]).astype(np.float32)
+    return out
+
+
+def chord2(X: np.ndarray, i, j) -> np.ndarray:
+    """Squared distance between the unit vectors of rows i and j in float64,
+    2 (1 - cos theta_ij), from the rows as given."""
+    Xi = X[np.asarray(i)].astype(np.float64)
+    Xj = X[np.asarray(j)].astype(np.float64)
+    ui = Xi / np.linalg.norm(Xi, axis=-1, keepdims=True)
+    uj = Xj / np.linalg.norm(Xj, axis=-1, keepdims=True)
+    diff = ui - uj
+    return np.einsum("...j,...j->...", diff, diff)
+
+
 # ---------------------------------------------------------------- distances
 def sqdist(X: np.ndarray, i, j) -> np.ndarray:
     """Squared Euclidean distance in float64."""
@@ -320,19 +365,95 @@ def propagate_round(X: np.ndarray, ids: np.ndarray, k: int, pairwise: bool = Tru
     return out_ids, out_d, U
 
 
+def propagate_best_first(X: np.ndarray, ids: np.ndarray, k: int, visit_max: int, pairwise: bool = True):
+    """One pass of the best-first neighbourhood propagation of Section 3.2
+    over the frozen graph G (R18).  For every p: a priority queue starts
+    with p's neighbours keyed by their distance to p; the nearest is popped
+    and each of its neighbours not seen yet is evaluated (its distance to p
+    computed) and pushed, until visit_max points have been evaluated or the
+    queue is empty.  The evaluated points are p's candidates; the better
+    ones replace its current neighbours.  With pairwise updating every
+    evaluated pair (p, o) also proposes p to o, as in `propagate_round`.
+    Returns (ids, D, V) with V[p] the number of points p evaluated."""
+    n = X.shape[0]
+    cand = []
+    V = np.zeros(n, dtype=np.int64)
+    for p in range(n):
+        nb = [int(q) for q in ids[p] if q != NONE]
+        seen = set(nb)
+        seen.add(p)
+        heap = [(float(sqdist(X, p, q)), q) for q in nb]
+        heapq.heapify(heap)
+        ev = []
+        budget = visit_max
+        while heap and budget > 0:
+            _, q = heapq.heappop(heap)
+            for o in ids[q]:
+                o = int(o)
+                if o == NONE or o in seen:
+                    continue
+                seen.add(o)
+                ev.append(o)
+                heapq.heappush(heap, (float(sqdist(X, p, o)), o))
+                budget -= 1
+                if budget == 0:
+                    break
+        cand.append(np.asarray(ev, dtype=np.uint32))
+        V[p] = len(ev)
+    rev = [[] for _ in range(n)]
+    if pairwise:
+        for u in range(n):
+            for o in cand[u]:
+                rev[int(o)].append(u)
+    out_ids = np.full((n, k), NONE, dtype=np.uint32)
+    out_d = np.full((n, k), np.inf, dtype=np.float64)
+    for p in range(n):
+        nb = ids[p][ids[p] != NONE]
+        r = np.asarray(rev[p], dtype=np.uint32)
+        r = r[(r != p) & ~np.isin(r, nb)]
+        allc = np.unique(np.concatenate([nb, cand[p], r]).astype(np.uint32))
+        out_ids[p], out_d[p] = _keep_k(allc, sqdist(X, np.full(len(allc), p), allc.astype(np.int64)), k)
+    return out_ids, out_d, V
+
+
 # ---------------------------------------------------------------- whole method
-def build(X: np.ndarray, p: Params, split: str = "rp", return_stages: bool = False):
-    """T divisions -> leaf k-NN per division -> merge -> p.rounds propagation rounds."""
-    lists, perms = [], []
+def build(X: np.ndarray, p: Params, split: str = "rp", return_stages: bool = False, metric: str = "l2",
+          visit_max: int = 0, rate_permille: int = 0):
+    """T divisions -> leaf k-NN per division -> merge -> p.rounds propagation
+    rounds (first-order rounds, or best-first passes when visit_max > 0).
+    metric "cos" runs the method on normalize_rows(X) (R20).  rate_permille
+    > 0 stops the divisions at the first m whose effective rate r_m falls
+    below rate_permille / 1000 (R19; T is then the largest number of
+    divisions)."""
+    if metric == "cos":
+        X = normalize_rows(X)
+    elif metric != "l2":
+        raise ValueError(metric)
+    lists, perms, rates = [], [], []
+    union = [set() for _ in range(p.n)]
+    total = 0
     for t in range(p.T):
         perm, off, _ = divide(X, p, t, split)
         li, _ = leaf_knn(X, perm, off, p.k)
         lists.append(li)
         perms.append(perm)
+        if rate_permille > 0:
+            new = 0
+            for i in range(p.n):
+                before = len(union[i])
+                union[i].update(int(x) for x in li[i] if x != NONE)
+                new += len(union[i]) - before
+            total += new
+            rates.append((new, total))
+            if 1000 * new < rate_permille * total:
+                break
     ids, dist = merge(X, lists, p.k)
-    stages = {"perms": perms, "lists": lists, "merged": (ids.copy(), dist.copy()), "rounds": []}
+    stages = {"perms": perms, "lists": lists, "merged": (ids.copy(), dist.copy()), "rounds": [], "rates": rates}
     for _ in range(p.rounds):
-        ids, dist, U = propagate_round(X, ids, p.k, p.pairwise)
+        if visit_max > 0:
+            ids, dist, U = propagate_best_first(X, ids, p.k, visit_max, p.pairwise)
+        else:
+            ids, dist, U = propagate_round(X, ids, p.k, p.pairwise)
         stages["rounds"].append((ids.copy(), dist.copy(), U))
     return (ids, dist, stages) if return_stages else (ids, dist)
 
