@@ -15,8 +15,9 @@
  *      (Section 3.1),
  *   3. the combination of the T base graphs: unite each point's adjacency
  *      lists and keep the k nearest (Section 3.1),
- *   4. neighbourhood propagation rounds (Section 3.2, first-order form of
- *      Theorem 1) with pairwise updating (Section 3.4).
+ *   4. neighbourhood propagation (Section 3.2): first-order rounds
+ *      (Theorem 1) or best-first passes with a budget of visited points,
+ *      with pairwise updating (Section 3.4).
  *
  * Conventions shared by every entry point
  *   - Array arguments are DEVICE pointers owned by the caller unless a
@@ -76,6 +77,14 @@ typedef enum {
 } knng_precision;
 
 typedef enum {
+  KNNG_METRIC_L2 = 0,     /* squared Euclidean distance                        */
+  KNNG_METRIC_COSINE = 1  /* cosine: the method runs on rows scaled to unit
+                             length (knng_normalize); distances are the
+                             squared distances of the unit rows,
+                             2 (1 - cos theta), which rank like 1 - cos theta */
+} knng_metric;
+
+typedef enum {
   KNNG_OP_DIVIDE = 0,
   KNNG_OP_LEAF = 1,
   KNNG_OP_MERGE = 2,
@@ -101,6 +110,19 @@ typedef struct {
   int32_t rerank_m;       /* extra leaf candidates re-ranked exactly (>= 0)    */
   int32_t pca_iters;      /* power iterations for KNNG_SPLIT_PCA (e.g. 16)     */
   uint64_t seed;          /* seed of every random draw                         */
+  int32_t metric;         /* knng_metric, honoured by knng_build* and the graph
+                             entry points; the stage entry points measure
+                             distances between the rows they are given       */
+  int32_t visit_max;      /* propagation form: 0 = first-order rounds
+                             (Theorem 1); > 0 = best-first passes (Section
+                             3.2) evaluating at most visit_max new points per
+                             point and pass (<= 1024)                        */
+  int32_t rate_permille;  /* 0: knng_build runs all T divisions; > 0: it stops
+                             them at the first division m whose effective rate
+                             r_m (Section 3.2) is below rate_permille / 1000
+                             (Section 4 starts propagation at r_m < 0.05,
+                             i.e. 50); T is then the largest number          */
+  int32_t reserved;       /* must be 0                                         */
 } knng_params;
 
 /* Diagnostics a call leaves in its workspace (read with knng_read_diag). */
@@ -109,6 +131,13 @@ typedef struct {
   int64_t leaf_rows;            /* leaf rows processed                        */
   int64_t prop_candidates;      /* sum over points of |C_p| in the last round */
   int64_t prop_proposals;       /* reverse proposals kept in the last round   */
+  int64_t divisions_used;       /* knng_build: divisions run (T unless the
+                                   effective-rate rule stopped them earlier) */
+  int64_t rate_new[64];         /* knng_build with rate_permille > 0: per
+                                   division m < 64, sum over p of the ids of
+                                   p's list m in none of its earlier lists   */
+  int64_t rate_total[64];       /* ... and of |union of p's lists 0..m|; r_m =
+                                   rate_new[m] / rate_total[m]               */
 } knng_diag;
 
 /* Human-readable name of a status code (static string). */
@@ -129,6 +158,13 @@ size_t knng_workspace_bytes(const knng_params* p, int op);
  *     permutation; `cap` is its capacity in elements.                      */
 int knng_tree_shape(const knng_params* p, int t, int64_t* leaf_off_host, int64_t cap, int64_t* n_leaves,
                     int64_t* n_internal, int32_t* depth);
+
+/* Rows scaled to unit length, for the cosine distance of Definition 1:
+ * Xn[i] = X[i] / |X[i]| with |X[i]|^2 summed over the features left to
+ * right in float32 (each product and sum rounded), a correctly rounded
+ * square root and correctly rounded quotients; a zero row stays zero.
+ * X, Xn: n x d (d a multiple of 4; Xn may equal X).  Asynchronous.          */
+int knng_normalize(int64_t n, int32_t d, const float* X, float* Xn, void* stream);
 
 /* One random division (Section 3.1; appendix for the random-projection
  * median split; Section 3.4 for the principal direction).  Every node with
@@ -178,11 +214,18 @@ int knng_leaf_knn_noalloc(const knng_params* p, const float* X, const uint32_t* 
 int knng_merge(const knng_params* p, int n_lists, const uint32_t* ids_in, const float* dist_in,
                uint32_t* ids_out, float* dist_out, void* stream);
 
-/* `rounds` rounds of neighbourhood propagation (Section 3.2) in the
- * first-order form of Theorem 1: each round reads the graph G frozen and
- * gives every p the first k by (distance, id) of N(p), the neighbours of its
- * neighbours and, when p->pairwise (Section 3.4), the points that evaluated
- * p as such a candidate.
+/* `rounds` rounds of neighbourhood propagation (Section 3.2).  Each round
+ * reads the graph G frozen.  With p->visit_max == 0 it is the first-order
+ * form of Theorem 1: every p gets the first k by (distance, id) of N(p) and
+ * the neighbours of its neighbours.  With p->visit_max > 0 it is a
+ * best-first pass: a queue ordered by (distance to p, id) starts with N(p);
+ * the nearest queued point is popped and its neighbours not seen yet are
+ * evaluated (distance to p) and queued, in its list order, until visit_max
+ * points have been evaluated or the queue is empty; p keeps the first k of
+ * N(p) and the evaluated points.  Either way, when p->pairwise (Section
+ * 3.4), the points that evaluated p are candidates of p too.
+ * First-order rounds take k <= 31 in one fast kernel and 31 < k <= 64 in the
+ * queue kernel; best-first passes take any k <= 64.
  *   ids, dist (n x k, in/out).                                             */
 int knng_propagate(const knng_params* p, const float* X, uint32_t* ids, float* dist, int rounds, void* ws,
                    size_t ws_bytes, void* stream);
@@ -199,9 +242,12 @@ int knng_build(const knng_params* p, const float* X, uint32_t* ids, float* dist,
 
 /* knng_build with a HIP event at every stage boundary; waits for the stream
  * at the end.  ms_out (host, at least 3 + rounds entries) receives the GPU
- * time of: all T divisions (entry 0, the batched divide launches), the leaf
- * k-NN of every leaf of every division (1, one persistent launch plus its
- * exact-row pass), the merge (2), then each propagation round (3 + r).     */
+ * time of: all T divisions (entry 0, the batched divide launches, and the
+ * row scaling of the cosine metric), the leaf k-NN of every leaf of every
+ * division (1, one persistent launch plus its exact-row pass), the merge
+ * (2), then each propagation round (3 + r).  With rate_permille > 0 the
+ * divisions run one at a time: entry 0 then holds the divide, leaf k-NN and
+ * rate test of every division and entry 1 is zero.                         */
 int knng_build_timed(const knng_params* p, const float* X, uint32_t* ids, float* dist, void* ws, size_t ws_bytes,
                      void* stream, float* ms_out, int ms_cap);
 

@@ -4,11 +4,11 @@ ABI of include/knng.h.  This package is the thin Python side: the ctypes
 binding plus torch helpers for device buffers."""
 from . import _lib
 from ._lib import (BF16, FP32, MLP_EMB, MLP_HIDDEN, NONE, OP_BUILD, OP_COLEAF, OP_DIVIDE, OP_LEAF, OP_MERGE,
-                   OP_PROPAGATE, NOALLOC_MAX_N, SPLIT_PCA, SPLIT_RP, BuildGraph, KnngError, Params, build, build_split, build_timed, coleaf_rate,
+                   OP_PROPAGATE, NOALLOC_MAX_N, SPLIT_PCA, SPLIT_RP, METRIC_L2, METRIC_COSINE, normalize, BuildGraph, KnngError, Params, build, build_split, build_timed, coleaf_rate,
                    divide, leaf_knn, leaf_knn_noalloc, leaf_set_config, leaf_tune, learned_choice, merge, mlp_adam, mlp_forward, mlp_grad, mlp_init, mlp_param_count,
                    mlp_sample_pairs, mlp_train, mlp_workspace_bytes, propagate, read_diag, tree_shape, workspace_bytes)
 
-__all__ = ["Params", "KnngError", "build", "build_split", "build_timed", "coleaf_rate", "learned_choice", "divide", "leaf_knn", "leaf_knn_noalloc", "merge",
+__all__ = ["Params", "KnngError", "build", "build_split", "build_timed", "coleaf_rate", "learned_choice", "divide", "leaf_knn", "leaf_knn_noalloc", "merge", "normalize", "METRIC_L2", "METRIC_COSINE",
            "propagate", "read_diag", "tree_shape", "workspace_bytes", "alloc_workspace", "knn_graph", "NONE", "FP32",
            "BF16", "SPLIT_RP", "SPLIT_PCA", "OP_DIVIDE", "OP_LEAF", "OP_MERGE", "OP_PROPAGATE", "OP_BUILD", "OP_COLEAF",
            "MLP_HIDDEN", "MLP_EMB", "mlp_param_count", "mlp_init", "mlp_forward", "mlp_workspace_bytes", "mlp_grad",
@@ -25,7 +25,11 @@ def alloc_workspace(p: Params, op: int, device="cuda"):
 
 def knn_graph(X, p: Params, ws=None):
     """Whole method on a resident (n, d) float32 CUDA tensor; returns
-    (ids int32-view of uint32 (n, k), dist float32 (n, k))."""
+    (ids int32-view of uint32 (n, k), dist float32 (n, k)).  The build is
+    enqueued on the current stream; a workspace allocated here returns to
+    torch's cache for that stream when this call returns, while the build
+    may still run: memory allocated afterwards must not be used on another
+    stream before the current one has been waited for."""
     import torch
     if ws is None:
         ws = alloc_workspace(p, OP_BUILD, X.device)

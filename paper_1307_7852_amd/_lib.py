@@ -18,6 +18,7 @@ NONE = 0xFFFFFFFF
 MAX_LEAF = 2048
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 SPLIT_RP, SPLIT_PCA = 0, 1
+METRIC_L2, METRIC_COSINE = 0, 1
 FP32, BF16 = 0, 1
 OP_DIVIDE, OP_LEAF, OP_MERGE, OP_PROPAGATE, OP_BUILD, OP_COLEAF = 0, 1, 2, 3, 4, 5
 MLP_HIDDEN, MLP_EMB = 256, 16
@@ -30,13 +31,16 @@ class _CParams(ctypes.Structure):
         ("leaf_max", ctypes.c_int32), ("leaf_cap_cycle", ctypes.c_int32), ("q_lo_pm", ctypes.c_int32),
         ("q_hi_pm", ctypes.c_int32), ("rounds", ctypes.c_int32), ("pairwise", ctypes.c_int32),
         ("split", ctypes.c_int32), ("precision", ctypes.c_int32), ("rerank_m", ctypes.c_int32),
-        ("pca_iters", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("pca_iters", ctypes.c_int32), ("seed", ctypes.c_uint64), ("metric", ctypes.c_int32),
+        ("visit_max", ctypes.c_int32), ("rate_permille", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
 class _CDiag(ctypes.Structure):
     _fields_ = [("leaf_rows_fallback", ctypes.c_int64), ("leaf_rows", ctypes.c_int64),
-                ("prop_candidates", ctypes.c_int64), ("prop_proposals", ctypes.c_int64)]
+                ("prop_candidates", ctypes.c_int64), ("prop_proposals", ctypes.c_int64),
+                ("divisions_used", ctypes.c_int64), ("rate_new", ctypes.c_int64 * 64),
+                ("rate_total", ctypes.c_int64 * 64)]
 
 
 @dataclass
@@ -57,6 +61,10 @@ class Params:
     rerank_m: int = 6
     pca_iters: int = 16
     seed: int = 0
+    metric: int = 0
+    visit_max: int = 0
+    rate_permille: int = 0
+    reserved: int = 0
 
     def c(self) -> _CParams:
         return _CParams(**{f.name: int(getattr(self, f.name)) for f in fields(self)})
@@ -86,6 +94,7 @@ def _load():
         "knng_status_str": (ctypes.c_char_p, [i32]),
         "knng_last_error": (ctypes.c_char_p, []),
         "knng_workspace_bytes": (sz, [P, i32]),
+        "knng_normalize": (i32, [i64, i32, vp, vp, vp]),
         "knng_tree_shape": (i32, [P, i32, ctypes.POINTER(i64), i64, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                   ctypes.POINTER(ctypes.c_int32)]),
         "knng_divide": (i32, [P, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
@@ -124,7 +133,7 @@ def _load():
 
 
 _lib = _load()
-EXPORTS = ["knng_status_str", "knng_last_error", "knng_workspace_bytes", "knng_tree_shape", "knng_divide",
+EXPORTS = ["knng_status_str", "knng_last_error", "knng_workspace_bytes", "knng_tree_shape", "knng_normalize", "knng_divide",
            "knng_leaf_knn", "knng_leaf_knn_noalloc", "knng_merge", "knng_propagate", "knng_build", "knng_read_diag", "knng_build_timed",
            "knng_build_split", "knng_coleaf_rate", "knng_learned_choice", "knng_mlp_param_count", "knng_mlp_init", "knng_mlp_forward",
            "knng_mlp_workspace_bytes", "knng_mlp_grad", "knng_mlp_adam", "knng_mlp_sample_pairs", "knng_mlp_train",
@@ -345,7 +354,18 @@ def read_diag(p: Params, ws, op: int, stream=None) -> dict:
     cp = p.c()
     out = _CDiag()
     _check(_lib.knng_read_diag(ctypes.byref(cp), _ptr(ws), op, ctypes.byref(out), _stream(stream)))
-    return {f[0]: getattr(out, f[0]) for f in _CDiag._fields_}
+    res = {}
+    for f in _CDiag._fields_:
+        v = getattr(out, f[0])
+        res[f[0]] = list(v) if f[0].startswith("rate_") else v
+    used = res["divisions_used"]
+    res["rate_new"], res["rate_total"] = res["rate_new"][:used], res["rate_total"][:used]
+    return res
+
+
+def normalize(X, Xn, stream=None):
+    """Rows of X scaled to unit length into Xn (the cosine metric's rows)."""
+    _check(_lib.knng_normalize(int(X.shape[0]), int(X.shape[1]), _ptr(X), _ptr(Xn), _stream(stream)))
 
 
 def raw():

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libknng.so")
 OBJ = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["knng_api.cpp", "divide.hip", "leaf.hip", "graph.hip", "mlp.hip"]
+SOURCES = ["knng_api.cpp", "divide.hip", "leaf.hip", "graph.hip", "mlp.hip", "rows.hip"]
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 FLAGS = ["-I", INCLUDE, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-mcode-object-version=5", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

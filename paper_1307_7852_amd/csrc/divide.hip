@@ -195,6 +195,7 @@ __device__ __forceinline__ float dot_seq_u8(const uint8_t* __restrict__ x, const
 
 // --------------------------------------------------------------- kernels
 __global__ __launch_bounds__(DIV_THREADS) void k_proj_hist0(DivideLevelArgs a) {
+  if (a.skip && *a.skip) return;   // uniform: a later division of a stopped build
   extern __shared__ float dir[];
   __shared__ uint32_t lh[HIST_B0];
   const ItemDesc it = a.items[blockIdx.x];
@@ -218,6 +219,7 @@ __global__ __launch_bounds__(DIV_THREADS) void k_proj_hist0(DivideLevelArgs a) {
 }
 
 __global__ __launch_bounds__(DIV_THREADS) void k_hist_pass(DivideLevelArgs a, int pass) {
+  if (a.skip && *a.skip) return;   // uniform: a later division of a stopped build
   __shared__ uint32_t lh[HIST_B1];
   __shared__ int sh[16];
   const ItemDesc it = a.items[blockIdx.x];
@@ -243,6 +245,7 @@ __global__ __launch_bounds__(DIV_THREADS) void k_hist_pass(DivideLevelArgs a, in
 }
 
 __global__ __launch_bounds__(DIV_THREADS) void k_part_count(DivideLevelArgs a) {
+  if (a.skip && *a.skip) return;   // uniform: a later division of a stopped build
   __shared__ int sh[16];
   const ItemDesc it = a.items[blockIdx.x];
   const SegDesc sd = a.segs[it.seg];
@@ -265,6 +268,7 @@ __global__ __launch_bounds__(DIV_THREADS) void k_part_count(DivideLevelArgs a) {
 }
 
 __global__ __launch_bounds__(DIV_THREADS) void k_part_scatter(DivideLevelArgs a) {
+  if (a.skip && *a.skip) return;   // uniform: a later division of a stopped build
   __shared__ int sh[16];
   const ItemDesc it = a.items[blockIdx.x];
   const size_t base = (size_t)it.slot * (size_t)a.n;
@@ -334,6 +338,7 @@ constexpr int PCA_LDS_DMAX = 136;   // 256 (d + 4) + 2d + 256 + 1024 floats fit 
 
 template <bool U8>
 __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
+  if (a.skip && *a.skip) return;   // uniform: a later division of a stopped build
   const bool u8 = a.X8 && (*a.flags & EXACT_U8) != 0u;   // uniform
   if (u8 != U8) return;
   extern __shared__ float smem[];
@@ -546,6 +551,7 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
 // global memory (L2) in every iteration; same sample, start, iterations and
 // sign rule as k_pca_lds.
 __global__ __launch_bounds__(DIV_THREADS) void k_pca_dirs(DivideLevelArgs a) {
+  if (a.skip && *a.skip) return;   // uniform: a later division of a stopped build
   extern __shared__ float smem[];
   const int d = a.d;
   float* mu = smem;               // d

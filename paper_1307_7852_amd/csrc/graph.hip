@@ -5,6 +5,8 @@
 // are bound by the gathers of neighbour lists and candidate rows.
 #include "knng_dev.h"
 
+#include <algorithm>
+
 namespace knng {
 
 namespace {
@@ -17,13 +19,14 @@ namespace {
 template <int R>
 __global__ __launch_bounds__(256) void k_merge(int64_t n, int k, int n_lists, const uint32_t* __restrict__ ids_in,
                                                 const float* __restrict__ dist_in, uint32_t* __restrict__ ids_out,
-                                                float* __restrict__ dist_out) {
+                                                float* __restrict__ dist_out, int64_t ls, int64_t rs,
+                                                const uint32_t* __restrict__ n_used) {
   __shared__ uint64_t sk[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t p = (int64_t)blockIdx.x * 4 + w;
   if (p >= n) return;
+  if (n_used) n_lists = min(n_lists, (int)*n_used);   // lists of divisions that ran
   const int tot = n_lists * k;
-  const size_t nk = (size_t)n * k;
   uint64_t v[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -31,7 +34,7 @@ __global__ __launch_bounds__(256) void k_merge(int64_t n, int k, int n_lists, co
     uint64_t key = ~0ull;
     if (e < tot) {
       int li = e / k, j = e % k;
-      size_t idx = (size_t)li * nk + (size_t)p * k + j;
+      size_t idx = (size_t)li * ls + (size_t)p * rs + j;
       key = pack_did(dist_in[idx], ids_in[idx]);
     }
     v[r] = key;
@@ -284,8 +287,8 @@ __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
     od[(size_t)p * k + lane] = key_dist(v[0]);
   }
   if (!a.pairwise) return;
-  // 4. reverse proposals into p's own k*k slots
-  uint32_t* slots = a.prop_buf + (size_t)p * k * k * 2;
+  // 4. reverse proposals into p's own slots
+  uint32_t* slots = a.prop_buf + (size_t)p * a.slot_cap * 2;
   int np = 0;
   for (int base = 0; base < U; base += 64) {
     int ci = base + lane;
@@ -369,7 +372,7 @@ __global__ __launch_bounds__(256) void k_prop_scatter(PropArgs a) {
   const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (p >= a.n) return;
   const uint32_t np = a.prop_n[p];
-  const uint32_t* slots = a.prop_buf + (size_t)p * a.k * a.k * 2;
+  const uint32_t* slots = a.prop_buf + (size_t)p * a.slot_cap * 2;
   for (uint32_t j = lane; j < np; j += 64) {
     uint32_t dst = slots[2 * j];
     uint32_t pos = a.offs[dst] + atomicSub(&a.cnt[dst], 1u) - 1u;
@@ -466,11 +469,331 @@ __global__ __launch_bounds__(256) void k_prop_final(PropArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- propagation, queue form
+// One wave per point p with a queue of (distance to p, id) keys and an
+// open-addressing table of the ids seen so far (p, N(p) and every evaluated
+// point), both in LDS.  Best-first pass (Section 3.2): the queue starts with
+// N(p); the smallest unpopped key is popped (a popped key keeps its slot with
+// bit 63 set) and its neighbours not seen yet are evaluated in list order
+// and queued, until visit_max points have been evaluated or nothing is left
+// to pop.  FIRST: the first-order round of Theorem 1 for k > 31 (only the
+// entries of N(p) are popped and nothing limits the evaluations: the
+// candidates are N(N(p)) minus p and N(p), as in k_prop_forward).  Then p
+// keeps the first k by (distance, id) of N(p) and the evaluated points, and
+// with pairwise updating proposes itself to every evaluated point whose
+// frozen k-th entry it beats.
+template <int NCH, bool FIRST>
+__global__ __launch_bounds__(256) void k_prop_queue(PropArgs a, int qcap, int log2_tbl, int wave_bytes) {
+  extern __shared__ __align__(16) unsigned char qsm[];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+  const int64_t vis = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * wpb + w;
+  if (vis >= a.n) return;   // whole waves; no workgroup barrier below
+  uint64_t* Q = (uint64_t*)(qsm + (size_t)w * wave_bytes);
+  uint32_t* ht = (uint32_t*)(Q + qcap);
+  const int tbl = 1 << log2_tbl;
+  const int64_t p = a.order ? (int64_t)a.order[vis] : vis;
+  const int k = a.k, d = a.d;
+  constexpr uint64_t POPPED = 1ull << 63;
+  for (int i = lane; i < tbl; i += 64) ht[i] = KNNG_NONE;
+  wave_sync();
+  auto slot0 = [&](uint32_t id) { return (id * 0x9E3779B1u) >> (32 - log2_tbl); };
+  auto seen = [&](uint32_t id) -> bool {   // ends: the table always has empty slots
+    for (uint32_t h = slot0(id);; h = (h + 1) & (tbl - 1)) {
+      const uint32_t x = ht[h];
+      if (x == id) return true;
+      if (x == KNNG_NONE) return false;
+    }
+  };
+  auto insert = [&](uint32_t id) {
+    for (uint32_t h = slot0(id);; h = (h + 1) & (tbl - 1)) {
+      const uint32_t old = atomicCAS(&ht[h], KNNG_NONE, id);
+      if (old == KNNG_NONE || old == id) return;
+    }
+  };
+  const uint32_t nb = lane < k ? a.ids_in[(size_t)p * k + lane] : KNNG_NONE;
+  const float nbd = lane < k ? a.dist_in[(size_t)p * k + lane] : __int_as_float(0x7F800000);
+  const bool valid = nb != KNNG_NONE;
+  if (valid) insert(nb);
+  wave_sync();
+  if (lane == 0) insert((uint32_t)p);
+  int nvalid;
+  const int vslot = wave_prefix_count(valid, lane, &nvalid);
+  if (valid) Q[vslot] = pack_did(nbd, nb);
+  wave_sync();
+
+  // p's row for the scoring: byte rows (see k_prop_forward) or float4 chunks
+  const int g = lane >> 4, gl = lane & 15;
+  constexpr int NB = NCH >= 3 ? 2 : 1;
+  const bool u8 = NCH >= 1 && NCH <= 4 && a.X8 && (a.diag->exact_flags & EXACT_U8) != 0u && (d & 7) == 0 &&
+                  d <= 128 * NB;   // uniform
+  const int nblk = d >> 3;
+  float xq[NB][8];
+  float4 xr[NCH > 0 ? NCH : 1];
+  if (u8) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int blk = gl + 16 * b;
+      uint2 v = make_uint2(0u, 0u);
+      if (blk < nblk) v = *(const uint2*)(a.X8 + (size_t)p * d + 8 * blk);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        xq[b][e] = (float)((v.x >> (8 * e)) & 0xFFu);
+        xq[b][4 + e] = (float)((v.y >> (8 * e)) & 0xFFu);
+      }
+    }
+  } else if constexpr (NCH > 0) {
+#pragma unroll
+    for (int i = 0; i < NCH; ++i) {
+      const int cc = gl + 16 * i;
+      xr[i] = (cc < (d >> 2)) ? ((const float4*)(a.X + (size_t)p * d))[cc] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  // scores the cnt candidates whose ids sit in Q[b0 .. b0 + cnt) and stores
+  // their (distance, id) keys there
+  auto score = [&](int b0, int cnt) {
+    if (u8) {
+      constexpr int R8 = 8;
+      for (int base = 0; base < cnt; base += 4 * R8) {
+        uint2 wr[R8][NB];
+#pragma unroll
+        for (int j = 0; j < R8; ++j) {
+          const int ci = base + g + 4 * j;
+          const uint32_t o = ci < cnt ? (uint32_t)Q[b0 + ci] : (uint32_t)p;
+          const uint8_t* yr = a.X8 + (size_t)o * d;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const int blk = gl + 16 * b;
+            wr[j][b] = *(const uint2*)(yr + 8 * (blk < nblk ? blk : 0));
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < R8; ++j) {
+          float acc = 0.f;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            float part = 0.f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const float y0 = (float)((wr[j][b].x >> (8 * e)) & 0xFFu), y1 = (float)((wr[j][b].y >> (8 * e)) & 0xFFu);
+              const float e0 = xq[b][e] - y0, e1 = xq[b][4 + e] - y1;
+              part = __builtin_fmaf(e0, e0, part);
+              part = __builtin_fmaf(e1, e1, part);
+            }
+            acc += gl + 16 * b < nblk ? part : 0.f;
+          }
+          acc += __shfl_xor(acc, 8, 16);
+          acc += __shfl_xor(acc, 4, 16);
+          acc += __shfl_xor(acc, 2, 16);
+          acc += __shfl_xor(acc, 1, 16);
+          const int ci = base + g + 4 * j;
+          if (gl == 0 && ci < cnt) Q[b0 + ci] = pack_did(acc, (uint32_t)Q[b0 + ci]);
+        }
+      }
+    } else if constexpr (NCH > 0) {
+      for (int base = 0; base < cnt; base += 16) {
+        const float* yr[4];
+        uint32_t oid[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int ci = base + g + 4 * j;
+          oid[j] = ci < cnt ? (uint32_t)Q[b0 + ci] : (uint32_t)p;
+          yr[j] = a.X + (size_t)oid[j] * d;
+        }
+        float dd[4];
+        dist2_g16_reg4<NCH>(xr, yr, d, gl, dd);
+        if (gl == 0) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (base + g + 4 * j < cnt) Q[b0 + base + g + 4 * j] = pack_did(dd[j], oid[j]);
+        }
+      }
+    } else {
+      const float* xp = a.X + (size_t)p * d;
+      for (int base = 0; base < cnt; base += 4) {
+        const int ci = base + g;
+        const uint32_t o = ci < cnt ? (uint32_t)Q[b0 + ci] : (uint32_t)p;
+        const float dd = dist2_g16(xp, a.X + (size_t)o * d, d, gl);
+        if (gl == 0 && ci < cnt) Q[b0 + ci] = pack_did(dd, o);
+      }
+    }
+    wave_sync();
+  };
+
+  int qlen = nvalid;
+  int budget = FIRST ? k * k : a.visit_max;
+  while (budget > 0) {
+    const int lim = FIRST ? nvalid : qlen;   // FIRST pops only the entries of N(p)
+    uint64_t mn = ~0ull;
+    for (int i = lane; i < lim; i += 64) {
+      const uint64_t x = Q[i];
+      mn = x < mn ? x : mn;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint64_t y = shfl_xor_u64(mn, o);
+      mn = y < mn ? y : mn;
+    }
+    if (mn & POPPED) break;   // uniform: every key popped (or none queued)
+    for (int i = lane; i < lim; i += 64)
+      if (Q[i] == mn) Q[i] = mn | POPPED;   // keys are unique: one owner
+    const uint32_t q = key_id(mn);
+    const uint32_t o = lane < k ? a.ids_in[(size_t)q * k + lane] : KNNG_NONE;
+    const bool fresh = o != KNNG_NONE && !seen(o);
+    int cnt;
+    const int rank = wave_prefix_count(fresh, lane, &cnt);
+    const int ntake = cnt < budget ? cnt : budget;
+    wave_sync();
+    if (fresh && rank < budget) {   // the first `budget` new ones in q's list order
+      insert(o);
+      Q[qlen + rank] = (uint64_t)o;
+    }
+    wave_sync();
+    score(qlen, ntake);
+    qlen += ntake;
+    budget -= ntake;
+  }
+  const int V = qlen - nvalid;
+  if (lane == 0) atomicAdd(&a.diag->prop_candidates[blockIdx.x & (DIAG_SLOTS - 1)], (unsigned long long)V);
+  // p keeps the first k of N(p) and the evaluated points; only keys below the
+  // current k-th can enter
+  uint64_t keep = lane < k ? pack_did(nbd, nb) : ~0ull;
+  uint64_t kth = shfl_u64(keep, k - 1);
+  for (int base = nvalid; base < qlen; base += 64) {
+    const int i = base + lane;
+    const uint64_t x = i < qlen ? (Q[i] & ~POPPED) : ~0ull;
+    const bool in = x < kth;
+    if (!__any(in)) continue;   // uniform
+    uint64_t v[2] = {keep, in ? x : ~0ull};
+    wave_bitonic<2, 128, uint64_t>(v, lane);
+    keep = lane < k ? v[0] : ~0ull;
+    kth = shfl_u64(keep, k - 1);
+  }
+  uint32_t* oi = a.pairwise ? a.fwd_ids : a.ids_out;
+  float* od = a.pairwise ? a.fwd_dist : a.dist_out;
+  if (lane < k) {
+    oi[(size_t)p * k + lane] = key_id(keep);
+    od[(size_t)p * k + lane] = key_dist(keep);
+  }
+  if (!a.pairwise) return;
+  uint32_t* slots = a.prop_buf + (size_t)p * a.slot_cap * 2;
+  int np = 0;
+  for (int base = nvalid; base < qlen; base += 64) {
+    const int i = base + lane;
+    bool ok = false;
+    uint32_t o = 0;
+    float dd = 0.f;
+    if (i < qlen) {
+      const uint64_t x = Q[i] & ~POPPED;
+      o = key_id(x);
+      dd = key_dist(x);
+      const uint32_t kid = a.ids_in[(size_t)o * k + k - 1];
+      const float kd = a.dist_in[(size_t)o * k + k - 1];
+      ok = pack_did(dd, (uint32_t)p) < pack_did(kd, kid);
+    }
+    int tot;
+    const int pre = np + wave_prefix_count(ok, lane, &tot);
+    if (ok) {
+      slots[2 * pre] = o;
+      slots[2 * pre + 1] = __float_as_uint(dd);
+      atomicAdd(&a.cnt[o], 1u);
+    }
+    np += tot;
+  }
+  if (lane == 0) {
+    a.prop_n[p] = (uint32_t)np;
+    atomicAdd(&a.diag->prop_proposals[blockIdx.x & (DIAG_SLOTS - 1)], (unsigned long long)np);
+  }
+}
+
+// ---------------------------------------------------------------- effective rate
+// Thread per point: the ids of p's list m that none of its lists 0..m-1
+// holds, summed over the workgroup and added to diag->rate_new[m].
+template <int KM>
+__global__ __launch_bounds__(256) void k_rate_count(int64_t n, int k, int m, const uint32_t* __restrict__ lists,
+                                                    int64_t ls, int64_t rs, DiagDev* diag) {
+  __shared__ unsigned long long part[4];
+  if (diag->stop) return;   // uniform: the rule has already fired
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  unsigned long long nw = 0;
+  if (p < n) {
+    uint32_t cur[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) cur[j] = j < k ? lists[(size_t)m * ls + (size_t)p * rs + j] : KNNG_NONE;
+    uint64_t found = 0;
+    for (int t = 0; t < m; ++t)
+      for (int jj = 0; jj < k; ++jj) {
+        const uint32_t x = lists[(size_t)t * ls + (size_t)p * rs + jj];
+        if (x == KNNG_NONE) continue;
+#pragma unroll
+        for (int j = 0; j < KM; ++j)
+          if (cur[j] == x) found |= 1ull << j;
+      }
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+      if (cur[j] != KNNG_NONE && !((found >> j) & 1ull)) ++nw;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) nw += shfl_xor_u64(nw, o);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = nw;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long s = part[0] + part[1] + part[2] + part[3];
+    if (s) atomicAdd(&diag->rate_new[m], s);
+  }
+}
+
+// r_m = new_m / total_m with total_m = total_{m-1} + new_m; the divisions
+// stop once 1000 new_m < rate_permille total_m (integer arithmetic).
+__global__ void k_rate_decide(DiagDev* diag, int m, int rate_permille) {
+  if (threadIdx.x != 0 || diag->stop) return;
+  const unsigned long long nw = diag->rate_new[m];
+  const unsigned long long tot = (m > 0 ? diag->rate_total[m - 1] : 0ull) + nw;
+  diag->rate_total[m] = tot;
+  diag->div_used = (unsigned)(m + 1);
+  if (1000ull * nw < (unsigned long long)rate_permille * tot) diag->stop = 1u;
+}
+
+template <int NCH, bool FIRST>
+hipError_t launch_queue_n(const PropArgs& a, hipStream_t s) {
+  const int budget0 = FIRST ? a.k * a.k : a.visit_max;
+  const int qcap = a.k + budget0;
+  const int ent = a.k + 1 + budget0;
+  int log2_tbl = 6;
+  while ((1 << log2_tbl) < ent + ent / 2) ++log2_tbl;
+  const int wave_bytes = (qcap * 8 + (4 << log2_tbl) + 15) & ~15;
+  const int wpb = std::max(1, std::min(4, (160 * 1024) / wave_bytes));
+  const size_t shm = (size_t)wpb * wave_bytes;
+  if (shm > 160 * 1024) return hipErrorInvalidValue;
+  auto kern = k_prop_queue<NCH, FIRST>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const unsigned blocks = (unsigned)((a.n + wpb - 1) / wpb);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), shm, s, a, qcap, log2_tbl, wave_bytes);
+  return hipGetLastError();
+}
+
+template <bool FIRST>
+hipError_t launch_queue(const PropArgs& a, hipStream_t s) {
+  const int nc = a.d / 4;
+  if (nc <= 16) return launch_queue_n<1, FIRST>(a, s);
+  if (nc <= 32) return launch_queue_n<2, FIRST>(a, s);
+  if (nc <= 64) return launch_queue_n<4, FIRST>(a, s);
+  if (nc <= 128) return launch_queue_n<8, FIRST>(a, s);
+  if (nc <= 256) return launch_queue_n<16, FIRST>(a, s);
+  return launch_queue_n<0, FIRST>(a, s);
+}
+
 template <int R>
 hipError_t launch_merge_r(int64_t n, int k, int n_lists, const uint32_t* ids_in, const float* dist_in,
-                          uint32_t* ids_out, float* dist_out, hipStream_t s) {
+                          uint32_t* ids_out, float* dist_out, hipStream_t s, int64_t ls, int64_t rs,
+                          const uint32_t* n_used) {
   unsigned blocks = (unsigned)((n + 3) / 4);
-  hipLaunchKernelGGL(k_merge<R>, dim3(blocks), dim3(256), 0, s, n, k, n_lists, ids_in, dist_in, ids_out, dist_out);
+  hipLaunchKernelGGL(k_merge<R>, dim3(blocks), dim3(256), 0, s, n, k, n_lists, ids_in, dist_in, ids_out, dist_out, ls,
+                     rs, n_used);
   return hipGetLastError();
 }
 
@@ -495,14 +818,27 @@ hipError_t launch_fwd_d(const PropArgs& a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_merge(int64_t n, int k, int n_lists, const uint32_t* ids_in, const float* dist_in,
-                        uint32_t* ids_out, float* dist_out, hipStream_t s) {
+                        uint32_t* ids_out, float* dist_out, hipStream_t s, int64_t ls, int64_t rs,
+                        const uint32_t* n_used) {
   int tot = n_lists * k;
-  if (tot <= 64) return launch_merge_r<1>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s);
-  if (tot <= 128) return launch_merge_r<2>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s);
-  if (tot <= 256) return launch_merge_r<4>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s);
-  if (tot <= 512) return launch_merge_r<8>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s);
-  if (tot <= 1024) return launch_merge_r<16>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s);
+  if (tot <= 64) return launch_merge_r<1>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s, ls, rs, n_used);
+  if (tot <= 128) return launch_merge_r<2>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s, ls, rs, n_used);
+  if (tot <= 256) return launch_merge_r<4>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s, ls, rs, n_used);
+  if (tot <= 512) return launch_merge_r<8>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s, ls, rs, n_used);
+  if (tot <= 1024) return launch_merge_r<16>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s, ls, rs, n_used);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_effective_rate(int64_t n, int k, int m, const uint32_t* lists_ids, int64_t ls, int64_t rs,
+                                 int rate_permille, DiagDev* diag, hipStream_t s) {
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (k <= 16) hipLaunchKernelGGL(k_rate_count<16>, dim3(blocks), dim3(256), 0, s, n, k, m, lists_ids, ls, rs, diag);
+  else if (k <= 32) hipLaunchKernelGGL(k_rate_count<32>, dim3(blocks), dim3(256), 0, s, n, k, m, lists_ids, ls, rs, diag);
+  else hipLaunchKernelGGL(k_rate_count<64>, dim3(blocks), dim3(256), 0, s, n, k, m, lists_ids, ls, rs, diag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rate_decide, dim3(1), dim3(64), 0, s, diag, m, rate_permille);
+  return hipGetLastError();
 }
 
 hipError_t launch_propagate_round(const PropArgs& a, hipStream_t s) {
@@ -514,7 +850,9 @@ hipError_t launch_propagate_round(const PropArgs& a, hipStream_t s) {
   // R1 registers hold the k^2 gathered ids, R2 the k + k^2 keys of the
   // final selection: the smallest power-of-two widths that fit
   int kk = a.k * a.k, kt = a.k * a.k + a.k;
-  if (kk <= 64 && kt <= 128) e = launch_fwd_d<1, 2>(a, s);
+  if (a.visit_max > 0) e = launch_queue<false>(a, s);
+  else if (kt > 1024) e = launch_queue<true>(a, s);
+  else if (kk <= 64 && kt <= 128) e = launch_fwd_d<1, 2>(a, s);
   else if (kk <= 128 && kt <= 128) e = launch_fwd_d<2, 2>(a, s);
   else if (kk <= 128 && kt <= 256) e = launch_fwd_d<2, 4>(a, s);
   else if (kk <= 256 && kt <= 256) e = launch_fwd_d<4, 4>(a, s);

@@ -57,6 +57,12 @@ int validate(const knng_params* p) {
   if (p->split == KNNG_SPLIT_PCA && (p->pca_iters < 1 || p->pca_iters > 1000))
     return fail(KNNG_EINVAL, "pca_iters=%d out of [1, 1000]", p->pca_iters);
   if (p->precision == KNNG_BF16 && p->d > 2048) return fail(KNNG_EINVAL, "BF16 leaf Gram needs d <= 2048 (got %d)", p->d);
+  if (p->metric != KNNG_METRIC_L2 && p->metric != KNNG_METRIC_COSINE)
+    return fail(KNNG_EINVAL, "metric=%d unknown", p->metric);
+  if (p->visit_max < 0 || p->visit_max > 1024) return fail(KNNG_EINVAL, "visit_max=%d out of [0, 1024]", p->visit_max);
+  if (p->rate_permille < 0 || p->rate_permille > 1000)
+    return fail(KNNG_EINVAL, "rate_permille=%d out of [0, 1000]", p->rate_permille);
+  if (p->reserved != 0) return fail(KNNG_EINVAL, "reserved must be 0");
   int64_t capmax = p->leaf_cap_cycle ? 2 * (int64_t)p->leaf_max : p->leaf_max;
   if (capmax > KNNG_MAX_LEAF && p->n > KNNG_MAX_LEAF)
     return fail(KNNG_EINVAL, "leaf cap %lld exceeds KNNG_MAX_LEAF=%d", (long long)capmax, KNNG_MAX_LEAF);
@@ -273,10 +279,13 @@ LeafLayout leaf_layout(const knng_params& p, int slots) {
 }
 
 struct PropLayout { size_t diag, tmp_ids, tmp_dist, fwd_ids, fwd_dist, prop, prop_n, cnt, offs, bsum, bucket, total; };
+// proposal slots per point: every evaluated candidate may propose
+int prop_slot_cap(const knng_params& p) { return std::max(p.k * p.k, p.visit_max); }
+
 PropLayout prop_layout(const knng_params& p) {
   PropLayout L; Carve c;
   size_t nk = (size_t)p.n * p.k;
-  size_t nkk = nk * p.k;
+  size_t nkk = (size_t)p.n * prop_slot_cap(p);
   L.diag = c.take(sizeof(DiagDev));
   L.tmp_ids = c.take(nk * 4);
   L.tmp_dist = c.take(nk * 4);
@@ -295,7 +304,10 @@ PropLayout prop_layout(const knng_params& p) {
 // knng_build: diag | plan blob | T lists | two T-slot permutation buffers |
 // per-point norms | one-byte copy of X | one region shared in turn by the
 // divide, leaf and propagation scratch
-struct BuildLayout { size_t diag, blob, lists_ids, lists_dist, permA, permB, pnorm, x8, shared, total; };
+// With the effective-rate rule the divisions run one at a time: the blob
+// region then holds each division's own plan, one after another.
+struct BuildLayout { size_t diag, blob, lists_ids, lists_dist, permA, permB, pnorm, x8, xn, shared, total;
+                     std::vector<size_t> blob_t; };
 int build_layout(const knng_params& p, BuildLayout& L) {
   int st;
   BatchPtr B = get_batch(p, all_divisions(p), &st);
@@ -304,12 +316,21 @@ int build_layout(const knng_params& p, BuildLayout& L) {
   Carve c;
   L.diag = c.take(sizeof(DiagDev));
   L.blob = c.take(B->blob.size());
+  L.blob_t.clear();
+  if (p.rate_permille > 0) {
+    for (int t = 0; t < p.T; ++t) {
+      BatchPtr Bt = get_batch(p, {t}, &st);
+      if (!Bt) return st;
+      L.blob_t.push_back(c.take(Bt->blob.size()));
+    }
+  }
   L.lists_ids = c.take(nk * 4 * p.T);
   L.lists_dist = c.take(nk * 4 * p.T);
   L.permA = c.take((size_t)p.n * 4 * p.T);
   L.permB = c.take((size_t)p.n * 4 * p.T);
   L.pnorm = c.take((size_t)p.n * 4);
   L.x8 = c.take((size_t)p.n * p.d);
+  L.xn = c.take(p.metric == KNNG_METRIC_COSINE ? (size_t)p.n * p.d * 4 : 0);
   size_t sh = std::max({div_scratch(p, *B).total, leaf_layout(p, p.T).total, prop_layout(p).total});
   L.shared = c.take(sh);
   L.total = c.off;
@@ -345,7 +366,7 @@ hipError_t zero_diag(void* diag, hipStream_t s) {
 // buf[depth % 2].
 int divide_core(const knng_params& p, const Batch& B, const char* blob_dev, const float* X, const float* dir_override,
                 float* dirs_out, uint32_t* buf0, uint32_t* buf1, char* scratch, hipStream_t s,
-                const uint8_t* x8 = nullptr, const uint32_t* flags = nullptr) {
+                const uint8_t* x8 = nullptr, const uint32_t* flags = nullptr, const uint32_t* skip = nullptr) {
   DivScratch L = div_scratch(p, B);
   uint32_t* ukeys = (uint32_t*)(scratch + L.ukeys);
   uint32_t* hist = (uint32_t*)(scratch + L.hist);
@@ -371,6 +392,7 @@ int divide_core(const knng_params& p, const Batch& B, const char* blob_dev, cons
     a.pca_dirs = pca;
     a.X8 = x8;
     a.flags = flags;
+    a.skip = skip;
     HIP_TRY(launch_divide_level(a, s));
   }
   return KNNG_OK;
@@ -420,6 +442,8 @@ int leaf_single(const knng_params& p, const float* X, const uint32_t* perm, cons
   a.X = X; a.n = p.n; a.d = p.d; a.k = p.k; a.kp = p.k + p.rerank_m; a.precision = p.precision;
   a.perm = perm; a.leaf_off = leaf_off; a.n_leaves = n_leaves;
   a.ids = ids; a.dist = dist;
+  a.list_row = p.k;
+  a.list_slot = (int64_t)p.n * p.k;
   a.fallback = (uint32_t*)(scratch + L.fallback);
   a.fallback_cap = (uint64_t)p.n;
   a.pnorm = (float*)(scratch + L.pnorm);
@@ -429,14 +453,18 @@ int leaf_single(const knng_params& p, const float* X, const uint32_t* perm, cons
   return KNNG_OK;
 }
 
+// The lists are point-major: point i's list of batch slot b starts at
+// (i * p.T + b) * k (the merge then reads each point's T lists in one piece).
 int leaf_batched(const knng_params& p, const Batch& B, const char* blob_dev, const float* X, const uint32_t* perms,
                  uint32_t* ids, float* dist, char* scratch, DiagDev* diag, hipStream_t s, int waves = -1, int kc = -1,
-                 bool prepare_only = false, float* pnorm_checked = nullptr) {
+                 bool prepare_only = false, float* pnorm_checked = nullptr, const uint32_t* skip = nullptr) {
   LeafLayout L = leaf_layout(p, B.slots);
   LeafArgs a{};
   a.X = X; a.n = p.n; a.d = p.d; a.k = p.k; a.kp = p.k + p.rerank_m; a.precision = p.precision;
   a.perm = perms;
   a.ids = ids; a.dist = dist;
+  a.list_row = (int64_t)p.T * p.k;
+  a.list_slot = p.k;
   a.work = (const LeafWork*)(blob_dev + B.off_work);
   a.n_work = (uint32_t)B.work.size();
   a.counter = (uint32_t*)(scratch + L.counter);
@@ -453,6 +481,7 @@ int leaf_batched(const knng_params& p, const Batch& B, const char* blob_dev, con
     a.kc = kc;
   }
   a.prepare_only = prepare_only;
+  a.skip = skip;
   hipError_t e = launch_leaf(a, s);
   if (e == hipErrorInvalidConfiguration || e == hipErrorInvalidValue)
     return fail(KNNG_EUNSUPPORTED, "leaf tile configuration (waves %d, kc %d) does not fit", a.waves, a.kc);
@@ -486,6 +515,8 @@ int prop_core(const knng_params& p, const float* X, uint32_t* ids, float* dist, 
     a.order = order;
     a.diag = diag;
     a.X8 = x8;
+    a.visit_max = p.visit_max;
+    a.slot_cap = prop_slot_cap(p);
     HIP_TRY(launch_propagate_round(a, s));
     if (after_round && !(r == rounds - 1 && rounds % 2 == 1)) HIP_TRY(after_round(r));
   }
@@ -725,7 +756,8 @@ int knng_merge(const knng_params* p, int n_lists, const uint32_t* ids_in, const 
   if (n_lists < 1 || n_lists > 1024) return fail(KNNG_EINVAL, "n_lists=%d out of [1, 1024]", n_lists);
   if (!ids_in || !dist_in || !ids_out || !dist_out) return fail(KNNG_EINVAL, "null array argument");
   if ((int64_t)n_lists * p->k > 1024) return fail(KNNG_EUNSUPPORTED, "n_lists * k = %d exceeds 1024", n_lists * p->k);
-  HIP_TRY(launch_merge(p->n, p->k, n_lists, ids_in, dist_in, ids_out, dist_out, (hipStream_t)stream));
+  HIP_TRY(launch_merge(p->n, p->k, n_lists, ids_in, dist_in, ids_out, dist_out, (hipStream_t)stream,
+                       (int64_t)p->n * p->k, p->k));
   return KNNG_OK;
 }
 
@@ -734,7 +766,6 @@ int knng_propagate(const knng_params* p, const float* X, uint32_t* ids, float* d
   int st = validate(p);
   if (st) return st;
   if (rounds < 0) return fail(KNNG_EINVAL, "rounds=%d < 0", rounds);
-  if (p->k > 31) return fail(KNNG_EUNSUPPORTED, "propagation supports k <= 31 (got %d)", p->k);
   if (!X || !ids || !dist || !ws) return fail(KNNG_EINVAL, "null array argument");
   if (!aligned16(X)) return fail(KNNG_EINVAL, "X must be 16-byte aligned");
   PropLayout L = prop_layout(*p);
@@ -760,18 +791,29 @@ static int build_impl(const knng_params* p, const float* X, const float* S, int 
   ps.d = ds;
   if (((uintptr_t)ws & 255) != 0) return fail(KNNG_EINVAL, "ws must be 256-byte aligned");
   if ((int64_t)p->T * p->k > 1024) return fail(KNNG_EUNSUPPORTED, "T * k = %d exceeds 1024", p->T * p->k);
-  if (p->rounds > 0 && p->k > 31) return fail(KNNG_EUNSUPPORTED, "propagation supports k <= 31 (got %d)", p->k);
+  if (p->rate_permille > 0 && p->T > 64) return fail(KNNG_EUNSUPPORTED, "the effective-rate rule takes T <= 64");
   BuildLayout BL;
   st = build_layout(*p, BL);
   if (st) return st;
   if (ws_bytes < BL.total) return fail(KNNG_ENOMEM, "build needs %zu workspace bytes, got %zu", BL.total, ws_bytes);
   BatchPtr B = get_batch(*p, all_divisions(*p), &st);
   if (!B) return st;
+  const bool adaptive = p->rate_permille > 0;
+  std::vector<BatchPtr> Bt;   // adaptive: one batch per division
+  if (adaptive)
+    for (int t = 0; t < p->T; ++t) {
+      Bt.push_back(get_batch(*p, {t}, &st));
+      if (!Bt.back()) return st;
+    }
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
   if (upload) {
-    st = upload_blob(*B, w + BL.blob, s);
-    if (st) return st;
+    if (adaptive) {
+      for (int t = 0; t < p->T; ++t)
+        if ((st = upload_blob(*Bt[t], w + BL.blob_t[t], s))) return st;
+    } else if ((st = upload_blob(*B, w + BL.blob, s))) {
+      return st;
+    }
   }
   DiagDev* diag = (DiagDev*)(w + BL.diag);
   HIP_TRY(zero_diag(diag, s));
@@ -784,21 +826,57 @@ static int build_impl(const knng_params* p, const float* X, const float* S, int 
   float* lists_dist = (float*)(w + BL.lists_dist);
   char* sh = w + BL.shared;
   HIP_TRY(mark(0));
+  // cosine metric: the whole method runs on the rows scaled to unit length
+  const float* Xm = X;
+  const float* Sm = S;
+  if (p->metric == KNNG_METRIC_COSINE) {
+    float* xn = (float*)(w + BL.xn);
+    HIP_TRY(launch_normalize(X, p->n, p->d, xn, s));
+    if (S == X) Sm = xn;
+    Xm = xn;
+  }
+  const bool same = Sm == Xm && ds == p->d;
   // one check of X serves every stage: exactness flags, row norms and the
   // one-byte copy that the divide and propagation read when it holds X
-  HIP_TRY(launch_data_check(X, p->n, p->d, &diag->exact_flags, pnorm, x8, s));
-  st = divide_core(ps, *B, w + BL.blob, S, nullptr, nullptr, permA, permB, sh, s, (S == X && ds == p->d) ? x8 : nullptr,
-                   &diag->exact_flags);
-  if (st) return st;
-  const uint32_t* perms = (B->depth % 2 == 0) ? permA : permB;
-  HIP_TRY(mark(1));
-  st = leaf_batched(*p, *B, w + BL.blob, X, perms, lists_ids, lists_dist, sh, diag, s, -1, -1, false, pnorm);
-  if (st) return st;
-  HIP_TRY(mark(2));
-  HIP_TRY(launch_merge(p->n, p->k, p->T, lists_ids, lists_dist, ids, dist, s));
+  HIP_TRY(launch_data_check(Xm, p->n, p->d, &diag->exact_flags, pnorm, x8, s));
+  const uint32_t* order = nullptr;   // division 0's leaf order: the propagation's visiting order
+  const uint32_t* n_used = nullptr;
+  if (!adaptive) {
+    st = divide_core(ps, *B, w + BL.blob, Sm, nullptr, nullptr, permA, permB, sh, s, same ? x8 : nullptr,
+                     &diag->exact_flags);
+    if (st) return st;
+    const uint32_t* perms = (B->depth % 2 == 0) ? permA : permB;
+    order = perms;
+    HIP_TRY(mark(1));
+    st = leaf_batched(*p, *B, w + BL.blob, Xm, perms, lists_ids, lists_dist, sh, diag, s, -1, -1, false, pnorm);
+    if (st) return st;
+    HIP_TRY(mark(2));
+  } else {
+    // Divisions one at a time (Section 4's trigger): after each, the
+    // effective rate of its lists decides on the device whether the next
+    // ones run; every kernel of a later division returns at once once the
+    // rule has fired, so the sequence stays asynchronous and capturable.
+    for (int t = 0; t < p->T; ++t) {
+      uint32_t* pa = permA + (size_t)t * p->n;
+      uint32_t* pb = permB + (size_t)t * p->n;
+      st = divide_core(ps, *Bt[t], w + BL.blob_t[t], Sm, nullptr, nullptr, pa, pb, sh, s, same ? x8 : nullptr,
+                       &diag->exact_flags, &diag->stop);
+      if (st) return st;
+      const uint32_t* perm_t = (Bt[t]->depth % 2 == 0) ? pa : pb;
+      if (t == 0) order = perm_t;
+      st = leaf_batched(*p, *Bt[t], w + BL.blob_t[t], Xm, perm_t, lists_ids + (size_t)t * p->k,
+                        lists_dist + (size_t)t * p->k, sh, diag, s, -1, -1, false, pnorm, &diag->stop);
+      if (st) return st;
+      HIP_TRY(launch_effective_rate(p->n, p->k, t, lists_ids, p->k, (int64_t)p->T * p->k, p->rate_permille, diag, s));
+    }
+    n_used = &diag->div_used;
+    HIP_TRY(mark(1));
+    HIP_TRY(mark(2));
+  }
+  HIP_TRY(launch_merge(p->n, p->k, p->T, lists_ids, lists_dist, ids, dist, s, p->k, (int64_t)p->T * p->k, n_used));
   HIP_TRY(mark(3));
   if (p->rounds > 0) {
-    st = prop_core(*p, X, ids, dist, p->rounds, sh, diag, perms, s, [&](int r) { return mark(4 + r); }, x8);
+    st = prop_core(*p, Xm, ids, dist, p->rounds, sh, diag, order, s, [&](int r) { return mark(4 + r); }, x8);
     if (st) return st;
   }
   return KNNG_OK;
@@ -1109,6 +1187,21 @@ int knng_read_diag(const knng_params* p, const void* ws, int op, knng_diag* out,
     out->prop_candidates += (int64_t)d.prop_candidates[i];
     out->prop_proposals += (int64_t)d.prop_proposals[i];
   }
+  out->divisions_used = op == KNNG_OP_BUILD ? (p->rate_permille > 0 ? (int64_t)d.div_used : (int64_t)p->T) : 0;
+  for (int i = 0; i < 64; ++i) {
+    out->rate_new[i] = (int64_t)d.rate_new[i];
+    out->rate_total[i] = (int64_t)d.rate_total[i];
+  }
+  return KNNG_OK;
+}
+
+int knng_normalize(int64_t n, int32_t d, const float* X, float* Xn, void* stream) {
+  if (n < 0 || n >= (int64_t)0xFFFFFFFFll) return fail(KNNG_EINVAL, "n=%lld out of [0, 2^32-1)", (long long)n);
+  if (d < 4 || d > 4096 || d % 4) return fail(KNNG_EINVAL, "d=%d must be a multiple of 4 in [4, 4096]", d);
+  if (n == 0) return KNNG_OK;
+  if (!X || !Xn) return fail(KNNG_EINVAL, "null array argument");
+  if (!aligned16(X) || !aligned16(Xn)) return fail(KNNG_EINVAL, "X and Xn must be 16-byte aligned");
+  HIP_TRY(launch_normalize(X, n, d, Xn, (hipStream_t)stream));
   return KNNG_OK;
 }
 

@@ -111,6 +111,11 @@ struct DiagDev {
   unsigned int pad;
   unsigned long long prop_candidates[DIAG_SLOTS];   // last round: sum of |C_p|
   unsigned long long prop_proposals[DIAG_SLOTS];    // last round: proposals kept
+  // effective-rate rule (build with rate_permille > 0)
+  unsigned long long rate_new[64];     // division m: ids of list m new to the union
+  unsigned long long rate_total[64];   // division m: size of the union after m
+  unsigned int div_used;               // divisions run so far
+  unsigned int stop;                   // 1 once the rule has stopped the divisions
 };
 
 // ------------------------------------------------------------------ launchers
@@ -133,6 +138,7 @@ struct DivideLevelArgs {
   float* pca_dirs;           // n_internal x d scratch when PCA
   const uint8_t* X8;         // nullable: one-byte copy of X, read instead of X when *flags has EXACT_U8
   const uint32_t* flags;
+  const uint32_t* skip;      // nullable: when *skip != 0 every kernel of the level returns at once
 };
 hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s);
 // compute units of the current device (cached after the first call)
@@ -142,6 +148,8 @@ struct LeafArgs {
   const float* X; int64_t n; int d; int k; int kp; int precision;
   const uint32_t* perm; const int64_t* leaf_off; int64_t n_leaves;   // single-division mode
   uint32_t* ids; float* dist;
+  int64_t list_row;          // elements from one point's list to the next (k: n x k rows)
+  int64_t list_slot;         // batched mode: elements from one division's lists to the next
   const LeafWork* work;      // batched mode (non-null): persistent workgroups pull leaves
   uint32_t n_work;
   uint32_t* counter;         // batched mode: next work item (zeroed by the launcher)
@@ -154,6 +162,7 @@ struct LeafArgs {
   int kc;                    // feature chunk staged per tile (32, 64, 128; 0: chosen from d)
   bool prepare_only;         // set kernel attributes and occupancy, launch nothing
   bool data_checked;         // diag->exact_flags and pnorm already hold this X's check
+  const uint32_t* skip;      // nullable: when *skip != 0 the leaf kernels return at once
 };
 hipError_t launch_leaf(const LeafArgs& a, hipStream_t s);
 // Data check of X: clears the EXACT_* bits of *flags (set them all first)
@@ -163,8 +172,23 @@ hipError_t launch_leaf(const LeafArgs& a, hipStream_t s);
 hipError_t launch_data_check(const float* X, int64_t n, int d, uint32_t* flags, float* pnorm, uint8_t* x8,
                              hipStream_t s);
 
+// Entry j of list li of point p sits at li * list_stride + p * row_stride + j
+// (the C ABI's n_lists x n x k: list_stride = n k, row_stride = k; the
+// build's point-major n x T x k: list_stride = k, row_stride = T k).
+// n_used (nullable, device): merge only the first *n_used lists.
 hipError_t launch_merge(int64_t n, int k, int n_lists, const uint32_t* ids_in, const float* dist_in,
-                        uint32_t* ids_out, float* dist_out, hipStream_t s);
+                        uint32_t* ids_out, float* dist_out, hipStream_t s, int64_t list_stride, int64_t row_stride,
+                        const uint32_t* n_used = nullptr);
+
+// Effective rate of division m (lists slot-major, n x k each): adds to
+// diag->rate_new[m] the ids of list m that none of lists 0..m-1 holds, sets
+// rate_total[m], counts the division in div_used and sets diag->stop when
+// 1000 * new < rate_permille * total.  Does nothing once diag->stop is set.
+hipError_t launch_effective_rate(int64_t n, int k, int m, const uint32_t* lists_ids, int64_t list_stride,
+                                 int64_t row_stride, int rate_permille, DiagDev* diag, hipStream_t s);
+
+// Rows of X scaled to unit length (cosine metric).
+hipError_t launch_normalize(const float* X, int64_t n, int d, float* Xn, hipStream_t s);
 
 struct PropArgs {
   const float* X; int64_t n; int d; int k; int pairwise;
@@ -180,6 +204,8 @@ struct PropArgs {
   const uint32_t* order;                  // nullable: the order points are processed in
   DiagDev* diag;
   const uint8_t* X8;                      // nullable: one-byte copy of X, scored from when diag->exact_flags has EXACT_U8
+  int visit_max;                          // > 0: best-first pass with this budget; 0: first-order round
+  int slot_cap;                           // proposal slots per point in prop_buf
 };
 hipError_t launch_propagate_round(const PropArgs& a, hipStream_t s);
 

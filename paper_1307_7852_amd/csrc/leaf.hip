@@ -590,8 +590,8 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
             const bool none = kk == KEY_NONE;
             if (j < k) sat = sat || (!none && (kk >> 11) >= KEY_DSAT);
             if (j < k && (j & 1) == h) {
-              ids_out[(size_t)qid * k + j] = none ? KNNG_NONE : S.ids[kk & POS_MASK];
-              dist_out[(size_t)qid * k + j] = none ? INF : (float)(kk >> 11);
+              ids_out[(size_t)qid * a.list_row + j] = none ? KNNG_NONE : S.ids[kk & POS_MASK];
+              dist_out[(size_t)qid * a.list_row + j] = none ? INF : (float)(kk >> 11);
             }
           }
           if (sat && h == 0) {
@@ -667,8 +667,8 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
       int qp = qbase + qj;
       if (qp < m && slot < k) {
         uint32_t qid = S.ids[qp];
-        ids_out[(size_t)qid * k + slot] = key_id(kv[r]);
-        dist_out[(size_t)qid * k + slot] = key_dist(kv[r]);
+        ids_out[(size_t)qid * a.list_row + slot] = key_id(kv[r]);
+        dist_out[(size_t)qid * a.list_row + slot] = key_dist(kv[r]);
         if (slot == k - 1) {
           // every candidate outside the list has a key at least the KP-th's
           uint32_t kl = S.lst[w][qj * LS + KP - 1];
@@ -715,6 +715,7 @@ __global__ __launch_bounds__((Cfg<KP, W>::THREADS)) void k_leaf(LeafArgs a) {
   using Sh = LeafShared<KC, KP, BF16, W>;
   Sh& S = *reinterpret_cast<Sh*>(smem_raw);
   __shared__ uint32_t next;
+  if (a.skip && *a.skip) return;   // uniform: a later division of a stopped build
   // the index of the following work item is taken when a leaf starts, so
   // the atomic's round trip overlaps the leaf's own loads
   if (a.work && threadIdx.x == 0) next = atomicAdd(a.counter, 1u);
@@ -741,8 +742,8 @@ __global__ __launch_bounds__((Cfg<KP, W>::THREADS)) void k_leaf(LeafArgs a) {
     if (a.work) {
       const LeafWork wk = a.work[idx];
       perm += (size_t)wk.slot * a.n;
-      ids_out += (size_t)wk.slot * a.n * a.k;
-      dist_out += (size_t)wk.slot * a.n * a.k;
+      ids_out += (size_t)wk.slot * a.list_slot;
+      dist_out += (size_t)wk.slot * a.list_slot;
       off = (int64_t)wk.off;
       m = (int)wk.m;
     } else {
@@ -763,6 +764,7 @@ __global__ __launch_bounds__((Cfg<KP, W>::THREADS)) void k_leaf(LeafArgs a) {
 __global__ __launch_bounds__(256) void k_leaf_exact(LeafArgs a) {
   __shared__ uint64_t keys[2048 + 64];
   __shared__ uint64_t best[64];
+  if (a.skip && *a.skip) return;   // uniform
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   unsigned long long cnt = a.diag->fallback_count;
   if (cnt > a.fallback_cap) cnt = a.fallback_cap;
@@ -777,8 +779,8 @@ __global__ __launch_bounds__(256) void k_leaf_exact(LeafArgs a) {
       off = (int64_t)wk.off;
       m = wk.m;
       perm += (size_t)wk.slot * a.n;
-      ids_out += (size_t)wk.slot * a.n * a.k;
-      dist_out += (size_t)wk.slot * a.n * a.k;
+      ids_out += (size_t)wk.slot * a.list_slot;
+      dist_out += (size_t)wk.slot * a.list_slot;
     } else {
       off = a.leaf_off[L];
       m = a.leaf_off[L + 1] - off;
@@ -828,8 +830,8 @@ __global__ __launch_bounds__(256) void k_leaf_exact(LeafArgs a) {
       __syncthreads();
     }
     if (tid < a.k) {
-      ids_out[(size_t)qid * a.k + tid] = key_id(best[tid]);
-      dist_out[(size_t)qid * a.k + tid] = key_dist(best[tid]);
+      ids_out[(size_t)qid * a.list_row + tid] = key_id(best[tid]);
+      dist_out[(size_t)qid * a.list_row + tid] = key_dist(best[tid]);
     }
     __syncthreads();
   }

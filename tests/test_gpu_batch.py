@@ -48,6 +48,10 @@ def _setup(name, dev):
 def test_graph_replays_match_eager(dev, name):
     X, kp = _setup(name, dev)
     ref_ids, ref_d = K.knn_graph(X, kp)
+    # the reference build's workspace returns to torch's cache for the
+    # current stream while its kernels still run; memory allocated next is
+    # used on another stream below, so wait for the reference first
+    torch.cuda.synchronize()
     ids = torch.empty_like(ref_ids)
     dist = torch.empty_like(ref_d)
     ws = K.alloc_workspace(kp, K.OP_BUILD, dev)
@@ -110,6 +114,7 @@ def test_every_tile_configuration_gives_the_same_lists(dev, name):
 def test_autotuner_choice_is_used_and_exact(dev):
     X, kp = _setup("even", dev)
     ref_ids, ref_d = K.knn_graph(X, kp)
+    torch.cuda.synchronize()   # ws below is used on another stream (see test_graph_replays_match_eager)
     ws = K.alloc_workspace(kp, K.OP_BUILD, dev)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
