@@ -45,6 +45,9 @@ class Workload:
     rerank_m: int = 6
     split: str = "rp"            # "rp": random projection; "pca": random principal direction;
                                  # "learned": principal direction of a trained embedding
+    metric: str = "l2"           # "l2" or "cos"
+    visit_max: int = 0           # > 0: best-first propagation with this budget
+    rate_permille: int = 0       # > 0: stop the divisions once r_m < rate / 1000 (T is the cap)
 
 
 WORKLOADS = {
@@ -70,6 +73,21 @@ WORKLOADS = {
                                split="learned"),
     "sift4m_learned": Workload("sift4m_learned", 4_000_000, 128, 10, 6, 512, 2, "sift", 4000, SEED_BASE + 5,
                                split="learned"),
+    # The GIST-like workload with the BF16 leaf Gram and FP32 re-rank of k + 16.
+    "gist1m_bf16": Workload("gist1m_bf16", 1_000_000, 960, 20, 8, 512, 3, "gist", 500, SEED_BASE + 4, split="pca",
+                            precision="bf16", rerank_m=16),
+    # The GIST-like workload with best-first propagation (budget 100 visited points per point and pass).
+    "gist1m_bestfirst": Workload("gist1m_bestfirst", 1_000_000, 960, 20, 8, 512, 3, "gist", 500, SEED_BASE + 4,
+                                 split="pca", visit_max=100),
+    # SIFT-like with best-first propagation.
+    "sift1m_bestfirst": Workload("sift1m_bestfirst", 1_000_000, 128, 10, 8, 512, 3, "sift", 1000, SEED_BASE + 2,
+                                 split="pca", visit_max=40),
+    # SIFT-like with the divisions stopped by the effective rate (r_m < 0.05, at most 16 divisions).
+    "sift1m_adaptive": Workload("sift1m_adaptive", 1_000_000, 128, 10, 16, 512, 3, "sift", 1000, SEED_BASE + 2,
+                                split="pca", rate_permille=50),
+    # SIFT-like under the cosine distance.
+    "sift1m_cos": Workload("sift1m_cos", 1_000_000, 128, 10, 8, 512, 3, "sift", 1000, SEED_BASE + 2, split="pca",
+                           metric="cos"),
 }
 
 

@@ -26,9 +26,10 @@
  *     `ws_bytes` bytes, which must be at least knng_workspace_bytes(p, op)
  *     and 256-byte aligned.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
- *     enqueued asynchronously; an entry point may wait for the stream to
- *     reach its own first copy (host-to-device upload of the data-independent
- *     tree plan) but never for work enqueued after it.
+ *     enqueued asynchronously and the entry points do not wait for the
+ *     stream (the data-independent tree plan is copied from pinned host
+ *     memory the library keeps until the copy has completed), except those
+ *     documented as returning host results or timings.
  *   - Arguments are validated on the host before anything is enqueued.  On a
  *     negative return nothing was enqueued, except KNNG_EHIP, after which the
  *     outputs are unspecified.  knng_last_error() describes the last failure
@@ -208,7 +209,9 @@ int knng_leaf_knn_noalloc(const knng_params* p, const float* X, const uint32_t* 
                           int64_t n_leaves, uint32_t* ids, float* dist, void* stream);
 
 /* Combination of base graphs (Section 3.1): per point, unite n_lists lists,
- * drop duplicate ids, keep the first k by (distance, id).
+ * drop duplicate ids, keep the first k by (distance, id).  Every input list
+ * is sorted by (distance, id) with its padding at the tail, as the other
+ * entry points write them, and one id carries one distance.
  *   ids_in, dist_in (n_lists x n x k); ids_out, dist_out (n x k), which must
  *   not overlap the inputs.                                                */
 int knng_merge(const knng_params* p, int n_lists, const uint32_t* ids_in, const float* dist_in,

@@ -103,6 +103,92 @@ __global__ __launch_bounds__(256) void k_merge(int64_t n, int k, int n_lists, co
   }
 }
 
+// Thread-per-point merge for the configured list lengths (k = 10, 20): the
+// thread keeps p's k best keys sorted in registers, starting from its first
+// list (sorted and duplicate-free), and walks every other list in order
+// until an entry no longer beats its current k-th (the rest of that list
+// cannot either).  An entry equal to a kept key is the same (distance, id)
+// pair found by another division and is skipped.  The first PF entries of
+// up to G lists are loaded together (8-byte pieces: k is even), so a thread
+// waits for memory once per group instead of once per entry; the rest of a
+// list is read only when its PF-th entry still entered.
+template <int K>
+__global__ __launch_bounds__(256) void k_merge_pt(int64_t n, int n_lists, const uint32_t* __restrict__ ids_in,
+                                                  const float* __restrict__ dist_in, uint32_t* __restrict__ ids_out,
+                                                  float* __restrict__ dist_out, int64_t ls, int64_t rs,
+                                                  const uint32_t* __restrict__ n_used) {
+  static_assert(K % 2 == 0, "pairs of entries are loaded together");
+  constexpr int PF = 4, G = 8;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= n) return;
+  if (n_used) n_lists = min(n_lists, (int)*n_used);
+  const uint32_t* ib = ids_in + (size_t)p * rs;
+  const float* db = dist_in + (size_t)p * rs;
+  uint64_t L[K];
+  {
+    uint2 iv[K / 2];
+    float2 dv[K / 2];
+#pragma unroll
+    for (int j = 0; j < K / 2; ++j) {
+      iv[j] = ((const uint2*)ib)[j];
+      dv[j] = ((const float2*)db)[j];
+    }
+#pragma unroll
+    for (int j = 0; j < K / 2; ++j) {
+      L[2 * j] = pack_did(dv[j].x, iv[j].x);
+      L[2 * j + 1] = pack_did(dv[j].y, iv[j].y);
+    }
+  }
+  auto insert = [&](uint64_t x) -> bool {   // false: x cannot enter (nor can anything after it)
+    if (x >= L[K - 1]) return false;
+    bool dup = false;
+#pragma unroll
+    for (int i = 0; i < K; ++i) dup = dup || x == L[i];
+    if (!dup) {
+#pragma unroll
+      for (int i = K - 1; i > 0; --i) L[i] = x < L[i - 1] ? L[i - 1] : (x < L[i] ? x : L[i]);
+      L[0] = x < L[0] ? x : L[0];
+    }
+    return true;
+  };
+  for (int t0 = 1; t0 < n_lists; t0 += G) {
+    uint2 iv[G][PF / 2];
+    float2 dv[G][PF / 2];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int t = t0 + g < n_lists ? t0 + g : 0;   // past the last list: re-read list 0 (ignored)
+#pragma unroll
+      for (int j = 0; j < PF / 2; ++j) {
+        iv[g][j] = ((const uint2*)(ib + (size_t)t * ls))[j];
+        dv[g][j] = ((const float2*)(db + (size_t)t * ls))[j];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (t0 + g >= n_lists) break;
+      bool more = true;
+#pragma unroll
+      for (int j = 0; j < PF / 2 && more; ++j) {
+        more = insert(pack_did(dv[g][j].x, iv[g][j].x));
+        if (more) more = insert(pack_did(dv[g][j].y, iv[g][j].y));
+      }
+      if (more) {   // the list's first PF entries all entered: read on
+        const uint32_t* it = ib + (size_t)(t0 + g) * ls;
+        const float* dt = db + (size_t)(t0 + g) * ls;
+        for (int j = PF; j < K; ++j)
+          if (!insert(pack_did(dt[j], it[j]))) break;
+      }
+    }
+  }
+  uint32_t* io = ids_out + (size_t)p * K;
+  float* dout = dist_out + (size_t)p * K;
+#pragma unroll
+  for (int j = 0; j < K / 2; ++j) {
+    ((uint2*)io)[j] = make_uint2(key_id(L[2 * j]), key_id(L[2 * j + 1]));
+    ((float2*)dout)[j] = make_float2(key_dist(L[2 * j]), key_dist(L[2 * j + 1]));
+  }
+}
+
 // ---------------------------------------------------------------- propagation, forward part
 // Blocks are dealt to the 8 XCDs round-robin; remapping block b to a
 // contiguous range per XCD keeps the points one XCD works on (and so the
@@ -820,6 +906,17 @@ hipError_t launch_fwd_d(const PropArgs& a, hipStream_t s) {
 hipError_t launch_merge(int64_t n, int k, int n_lists, const uint32_t* ids_in, const float* dist_in,
                         uint32_t* ids_out, float* dist_out, hipStream_t s, int64_t ls, int64_t rs,
                         const uint32_t* n_used) {
+  const bool al8 = (((uintptr_t)ids_in | (uintptr_t)dist_in | (uintptr_t)ids_out | (uintptr_t)dist_out) & 7) == 0;
+  if ((k == 10 || k == 20) && al8) {
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (k == 10)
+      hipLaunchKernelGGL(k_merge_pt<10>, dim3(blocks), dim3(256), 0, s, n, n_lists, ids_in, dist_in, ids_out, dist_out,
+                         ls, rs, n_used);
+    else
+      hipLaunchKernelGGL(k_merge_pt<20>, dim3(blocks), dim3(256), 0, s, n, n_lists, ids_in, dist_in, ids_out, dist_out,
+                         ls, rs, n_used);
+    return hipGetLastError();
+  }
   int tot = n_lists * k;
   if (tot <= 64) return launch_merge_r<1>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s, ls, rs, n_used);
   if (tot <= 128) return launch_merge_r<2>(n, k, n_lists, ids_in, dist_in, ids_out, dist_out, s, ls, rs, n_used);

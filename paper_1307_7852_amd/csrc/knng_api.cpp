@@ -98,6 +98,54 @@ PlanPtr get_plan(const knng_params& p, int t, int* status) {
   return pl;
 }
 
+// ------------------------------------------------------------------ pinned plan images
+// A batch's device image lives in pinned host memory, so its upload is an
+// asynchronous copy and no entry point waits for the stream.  The memory is
+// released only after every copy recorded against it has completed: a freed
+// image goes to a list that is checked, without waiting, whenever a batch is
+// built.  An image copied while its stream was being captured into a graph
+// is kept until the process ends (the graph may replay the copy).
+struct HostBuf {
+  char* p = nullptr;
+  size_t n = 0;
+  bool keep = false;
+  std::mutex mu;
+  std::vector<hipEvent_t> pending;   // one event recorded after each copy from p
+  ~HostBuf();
+};
+struct Grave { char* p; std::vector<hipEvent_t> ev; };
+std::mutex g_grave_mu;
+std::vector<Grave> g_grave;
+
+bool copies_done(std::vector<hipEvent_t>& ev) {
+  for (size_t i = 0; i < ev.size();) {
+    if (hipEventQuery(ev[i]) == hipErrorNotReady) return false;
+    (void)hipEventDestroy(ev[i]);
+    ev[i] = ev.back();
+    ev.pop_back();
+  }
+  return true;
+}
+
+void reap_host_bufs() {
+  std::lock_guard<std::mutex> lk(g_grave_mu);
+  for (size_t i = 0; i < g_grave.size();) {
+    if (copies_done(g_grave[i].ev)) {
+      (void)hipHostFree(g_grave[i].p);
+      g_grave[i] = std::move(g_grave.back());
+      g_grave.pop_back();
+    } else {
+      ++i;
+    }
+  }
+}
+
+HostBuf::~HostBuf() {
+  if (!p || keep) return;
+  std::lock_guard<std::mutex> lk(g_grave_mu);
+  g_grave.push_back({p, std::move(pending)});
+}
+
 // ------------------------------------------------------------------ batched plans
 // A batch runs several divisions level by level: level l of the batch holds
 // every division's internal nodes at depth l (each tagged with its division
@@ -118,6 +166,7 @@ struct Batch {
   uint32_t max_segs = 0, max_items = 0;
   size_t off_items = 0, off_work = 0, off_leaf = 0;
   std::vector<char> blob;           // device image: segs | items | work | leaf_off0
+  std::shared_ptr<HostBuf> pinned;  // the same image in pinned host memory (null if pinning failed)
 };
 using BatchPtr = std::shared_ptr<const Batch>;
 
@@ -213,6 +262,17 @@ int make_batch(const knng_params& p, const std::vector<int>& ts, Batch& B) {
   if (!B.items.empty()) memcpy(B.blob.data() + B.off_items, B.items.data(), B.items.size() * sizeof(ItemDesc));
   if (!B.work.empty()) memcpy(B.blob.data() + B.off_work, B.work.data(), B.work.size() * sizeof(LeafWork));
   memcpy(B.blob.data() + B.off_leaf, B.leaf_off0.data(), B.leaf_off0.size() * 8);
+  reap_host_bufs();
+  auto hb = std::make_shared<HostBuf>();
+  void* hp = nullptr;
+  if (hipHostMalloc(&hp, B.blob.size(), hipHostMallocDefault) == hipSuccess && hp) {
+    memcpy(hp, B.blob.data(), B.blob.size());
+    hb->p = (char*)hp;
+    hb->n = B.blob.size();
+    B.pinned = hb;
+  } else {
+    (void)hipGetLastError();   // pageable fallback: upload_blob then waits for its copy
+  }
   return KNNG_OK;
 }
 
@@ -399,8 +459,29 @@ int divide_core(const knng_params& p, const Batch& B, const char* blob_dev, cons
 }
 
 int upload_blob(const Batch& B, char* dst, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(dst, B.blob.data(), B.blob.size(), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));   // the source may be dropped from the cache after this call
+  if (!B.pinned) {   // pageable image: the source may be dropped from the cache after this call
+    HIP_TRY(hipMemcpyAsync(dst, B.blob.data(), B.blob.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return KNNG_OK;
+  }
+  HostBuf& hb = *B.pinned;
+  HIP_TRY(hipMemcpyAsync(dst, hb.p, hb.n, hipMemcpyHostToDevice, s));
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(s, &cs));
+  std::lock_guard<std::mutex> lk(hb.mu);
+  if (cs != hipStreamCaptureStatusNone) {   // a graph may replay this copy: keep the image
+    hb.keep = true;
+    return KNNG_OK;
+  }
+  hipEvent_t e;
+  HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  hipError_t er = hipEventRecord(e, s);
+  if (er != hipSuccess) {
+    (void)hipEventDestroy(e);
+    return fail(KNNG_EHIP, "hipEventRecord failed: %s", hipGetErrorString(er));
+  }
+  copies_done(hb.pending);   // drops the events of finished copies
+  hb.pending.push_back(e);
   return KNNG_OK;
 }
 
