@@ -73,9 +73,9 @@ WORKLOADS = {
                                split="learned"),
     "sift4m_learned": Workload("sift4m_learned", 4_000_000, 128, 10, 6, 512, 2, "sift", 4000, SEED_BASE + 5,
                                split="learned"),
-    # The GIST-like workload with the BF16 leaf Gram and FP32 re-rank of k + 16.
+    # The GIST-like workload with the BF16 leaf Gram and FP32 re-rank of k + 12 (lists of 32 keys).
     "gist1m_bf16": Workload("gist1m_bf16", 1_000_000, 960, 20, 8, 512, 3, "gist", 500, SEED_BASE + 4, split="pca",
-                            precision="bf16", rerank_m=16),
+                            precision="bf16", rerank_m=12),
     # The GIST-like workload with best-first propagation (budget 100 visited points per point and pass).
     "gist1m_bestfirst": Workload("gist1m_bestfirst", 1_000_000, 960, 20, 8, 512, 3, "gist", 500, SEED_BASE + 4,
                                  split="pca", visit_max=100),

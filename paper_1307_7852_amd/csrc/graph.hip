@@ -384,9 +384,7 @@ __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
     if (ci < U) {
       o = cand_s[w][ci];
       dd = cd_s[w][ci];
-      uint32_t kid = a.ids_in[(size_t)o * k + k - 1];
-      float kd = a.dist_in[(size_t)o * k + k - 1];
-      ok = pack_did(dd, (uint32_t)p) < pack_did(kd, kid);
+      ok = pack_did(dd, (uint32_t)p) < a.kth[o];
     }
     int tot;
     int pre = np + wave_prefix_count(ok, lane, &tot);
@@ -401,6 +399,15 @@ __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
     a.prop_n[p] = (uint32_t)np;
     atomicAdd(&a.diag->prop_proposals[blockIdx.x & (DIAG_SLOTS - 1)], (unsigned long long)np);
   }
+}
+
+// Every point's frozen k-th key, packed: the proposal test reads this
+// dense n x 8-byte array instead of two scattered words of the lists.
+__global__ __launch_bounds__(256) void k_prop_kth(PropArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= a.n) return;
+  const size_t e = (size_t)p * a.k + a.k - 1;
+  a.kth[p] = pack_did(a.dist_in[e], a.ids_in[e]);
 }
 
 // ---------------------------------------------------------------- scan (exclusive, n+1 entries)
@@ -772,9 +779,7 @@ __global__ __launch_bounds__(256) void k_prop_queue(PropArgs a, int qcap, int lo
       const uint64_t x = Q[i] & ~POPPED;
       o = key_id(x);
       dd = key_dist(x);
-      const uint32_t kid = a.ids_in[(size_t)o * k + k - 1];
-      const float kd = a.dist_in[(size_t)o * k + k - 1];
-      ok = pack_did(dd, (uint32_t)p) < pack_did(kd, kid);
+      ok = pack_did(dd, (uint32_t)p) < a.kth[o];
     }
     int tot;
     const int pre = np + wave_prefix_count(ok, lane, &tot);
@@ -943,6 +948,8 @@ hipError_t launch_propagate_round(const PropArgs& a, hipStream_t s) {
   if ((e = launch_fill_u32((uint32_t*)a.diag->prop_candidates, 0u, 4 * DIAG_SLOTS, s)) != hipSuccess) return e;
   if (a.pairwise) {
     if ((e = launch_fill_u32(a.cnt, 0u, (size_t)a.n + 1, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_prop_kth, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   // R1 registers hold the k^2 gathered ids, R2 the k + k^2 keys of the
   // final selection: the smallest power-of-two widths that fit

@@ -338,7 +338,7 @@ LeafLayout leaf_layout(const knng_params& p, int slots) {
   return L;
 }
 
-struct PropLayout { size_t diag, tmp_ids, tmp_dist, fwd_ids, fwd_dist, prop, prop_n, cnt, offs, bsum, bucket, total; };
+struct PropLayout { size_t diag, tmp_ids, tmp_dist, fwd_ids, fwd_dist, prop, prop_n, cnt, offs, bsum, bucket, kth, total; };
 // proposal slots per point: every evaluated candidate may propose
 int prop_slot_cap(const knng_params& p) { return std::max(p.k * p.k, p.visit_max); }
 
@@ -357,6 +357,7 @@ PropLayout prop_layout(const knng_params& p) {
   L.offs = c.take(((size_t)p.n + 1) * 4);
   L.bsum = c.take((((size_t)p.n + 1 + 1023) / 1024 + 1024) * 4);
   L.bucket = c.take(p.pairwise ? nkk * 2 * 4 : 0);
+  L.kth = c.take(p.pairwise ? (size_t)p.n * 8 : 0);
   L.total = c.off;
   return L;
 }
@@ -593,6 +594,7 @@ int prop_core(const knng_params& p, const float* X, uint32_t* ids, float* dist, 
     a.offs = (uint32_t*)(ws + L.offs);
     a.block_sums = (uint32_t*)(ws + L.bsum);
     a.bucket = (uint32_t*)(ws + L.bucket);
+    a.kth = (uint64_t*)(ws + L.kth);
     a.order = order;
     a.diag = diag;
     a.X8 = x8;

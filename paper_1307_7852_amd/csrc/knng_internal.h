@@ -204,6 +204,7 @@ struct PropArgs {
   const uint32_t* order;                  // nullable: the order points are processed in
   DiagDev* diag;
   const uint8_t* X8;                      // nullable: one-byte copy of X, scored from when diag->exact_flags has EXACT_U8
+  uint64_t* kth;                          // pairwise: every point's frozen k-th (distance, id) key
   int visit_max;                          // > 0: best-first pass with this budget; 0: first-order round
   int slot_cap;                           // proposal slots per point in prop_buf
 };

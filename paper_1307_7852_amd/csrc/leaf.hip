@@ -172,11 +172,22 @@ struct QFrag {
         f[i] = (ok && c < d) ? *(const float4*)(row + c) : make_float4(0.f, 0.f, 0.f, 0.f);
       }
     } else {
+      // two 16-byte loads per 8 features (d is a multiple of 4, rows and c
+      // are 16-byte aligned), centred with the leaf mean and rounded
 #pragma unroll
       for (int i = 0; i < N8; ++i) {
-        int c = kc + h * HALF + 8 * i;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) b[i][e] = (__bf16)((ok && c + e < d) ? row[c + e] - mu[c + e] : 0.f);
+        const int c = kc + h * HALF + 8 * i;
+        const bool ok0 = ok && c < d, ok1 = ok && c + 4 < d;
+        const float4 v0 = ok0 ? *(const float4*)(row + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 v1 = ok1 ? *(const float4*)(row + c + 4) : make_float4(0.f, 0.f, 0.f, 0.f);
+        b[i][0] = (__bf16)(ok0 ? v0.x - mu[c] : 0.f);
+        b[i][1] = (__bf16)(ok0 ? v0.y - mu[c + 1] : 0.f);
+        b[i][2] = (__bf16)(ok0 ? v0.z - mu[c + 2] : 0.f);
+        b[i][3] = (__bf16)(ok0 ? v0.w - mu[c + 3] : 0.f);
+        b[i][4] = (__bf16)(ok1 ? v1.x - mu[c + 4] : 0.f);
+        b[i][5] = (__bf16)(ok1 ? v1.y - mu[c + 5] : 0.f);
+        b[i][6] = (__bf16)(ok1 ? v1.z - mu[c + 6] : 0.f);
+        b[i][7] = (__bf16)(ok1 ? v1.w - mu[c + 7] : 0.f);
       }
     }
   }
