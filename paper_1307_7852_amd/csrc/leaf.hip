@@ -408,6 +408,11 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
   // barrier between them orders both.  A pass followed by another over the
   // same leaf stages that pass's first two tiles in its last two steps;
   // bufbase keeps the buffer rotation running across passes.
+  // BF16 steps are short (one BF16 MFMA does the work of eight FP32 ones),
+  // so there a tile's global loads are issued one step earlier still: the
+  // loads of step st feed the store of step st + 1, carried in `pend`.
+  constexpr bool DEEP = BF16 && KP <= 16;   // (with longer lists the registers run out)
+  float4 pend[STAGE_F4];
   int bufbase = 0;
   bool staged = false;
   for (int qb = 0; qb < m; qb += C::QPB) {
@@ -469,6 +474,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
         stage_load(s0, rg);
         stage_store(s0, (s0 + bufbase) % TILE_BUFS, rg, first && !pre_norms);
       }
+      if constexpr (DEEP) stage_load(2 < nsteps ? 2 : 0, pend);   // the tile step 0 stores
     }
     __syncthreads();
     for (int st = 0; st < nsteps; ++st) {
@@ -485,7 +491,15 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
       const bool more = ahead < nsteps;
       const bool carry = !more && follow && nsteps >= 2;   // the next pass's step ahead - nsteps
       const int nxt = more ? ahead : carry ? ahead - nsteps : st;
-      stage_load(nxt, rg);
+      if constexpr (DEEP) {
+        // this step loads the tile the next step stores (step st + 3, in
+        // this pass or the next) and stores the one loaded by the last step
+        const int ahead3 = st + 3;
+        const int nxt3 = ahead3 < nsteps ? ahead3 : (follow && nsteps >= 4) ? ahead3 - nsteps : st;
+        stage_load(nxt3, rg);
+      } else {
+        stage_load(nxt, rg);
+      }
       if (wave_on) {
         if (kci == 0) {
 #pragma unroll
@@ -560,7 +574,13 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
           }
         }
       }
-      stage_store(nxt, (ahead + bufbase) % TILE_BUFS, rg, first && more && !pre_norms);
+      if constexpr (DEEP) {
+        stage_store(nxt, (ahead + bufbase) % TILE_BUFS, pend, first && more && !pre_norms);
+#pragma unroll
+        for (int u = 0; u < STAGE_F4; ++u) pend[u] = rg[u];
+      } else {
+        stage_store(nxt, (ahead + bufbase) % TILE_BUFS, rg, first && more && !pre_norms);
+      }
       if ((st & 1) || st + 1 == nsteps) __syncthreads();
     }
     staged = follow && nsteps >= 2;
