@@ -15,6 +15,8 @@
 // element (i, j) sits in lane 32*((i/4)%2) + j, register 4*(i/8) + i%4.
 #include "knng_dev.h"
 
+#include <algorithm>
+
 namespace knng {
 
 namespace {
@@ -129,6 +131,83 @@ __global__ __launch_bounds__(WG) void k_mlp_fwd(MlpArgs a) {
       const int e0 = 8 * g + 4 * h;
       *(float4*)(z + e0) = make_float4(zacc[4 * g] + b2[e0], zacc[4 * g + 1] + b2[e0 + 1], zacc[4 * g + 2] + b2[e0 + 2],
                                        zacc[4 * g + 3] + b2[e0 + 3]);
+    }
+  }
+}
+
+// Inference in BF16 (the embedding pass of a learned build): the same
+// products as k_mlp_fwd<true, false, NS>, with the network's weights rounded
+// to bfloat16 once per workgroup into LDS (rows padded by 8 halves) instead
+// of being re-read from global memory by every wave.  Workgroups stride over
+// tiles of 128 data rows.  Rounding a weight before or inside the MFMA's
+// operand conversion gives the same bfloat16, so the result is bit for bit
+// that of k_mlp_fwd.
+template <int NS>
+__global__ __launch_bounds__(WG) void k_mlp_embed(MlpArgs a, int64_t n_tiles) {
+  constexpr int DP = NS * 16 + 8;
+  __shared__ __bf16 w1s[MH * DP];
+  __shared__ __bf16 w2s[ME * (MH + 8)];
+  __shared__ float b1s[MH], b2s[ME];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, h = lane >> 5, c32 = lane & 31;
+  const int d = a.d;
+  const float* W1 = a.params;
+  const float* b1 = W1 + (size_t)MH * d;
+  const float* W2 = b1 + MH;
+  const float* b2 = W2 + (size_t)ME * MH;
+  for (int e = threadIdx.x; e < MH * NS * 16; e += WG) {
+    const int r = e / (NS * 16), c = e % (NS * 16);
+    w1s[r * DP + c] = (__bf16)(c < d ? W1[(size_t)r * d + c] : 0.f);
+  }
+  for (int e = threadIdx.x; e < ME * MH; e += WG) w2s[(e / MH) * (MH + 8) + e % MH] = (__bf16)W2[e];
+  for (int e = threadIdx.x; e < MH; e += WG) b1s[e] = b1[e];
+  if (threadIdx.x < ME) b2s[threadIdx.x] = b2[threadIdx.x];
+  __syncthreads();
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t row = tile * 128 + w * 32 + c32;
+    const bool ok = row < a.R;
+    const float* x = a.X + (ok ? row : 0) * d;
+    bf16x8 xb[NS];
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2) {
+      float xf[8];
+      const int f = 16 * s2 + 8 * h;
+      load8(xf, x + f, ok && f < d);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xb[s2][e] = (__bf16)(xf[e] * a.scale);
+    }
+    f32x16 zacc = {0};
+#pragma unroll 1
+    for (int t = 0; t < MH / 32; ++t) {
+      f32x16 acc = {0};
+      const __bf16* w1row = w1s + (t * 32 + c32) * DP;
+#pragma unroll
+      for (int s2 = 0; s2 < NS; ++s2) {
+        const bf16x8 wb = *(const bf16x8*)(w1row + 16 * s2 + 8 * h);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wb, xb[s2], acc, 0, 0, 0);
+      }
+      float hv[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) hv[r] = fmaxf(acc[r] + b1s[t * 32 + tile_row(r, h)], 0.f);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        bf16x8 av, bv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          bv[e] = (__bf16)hv[8 * q + e];
+          const int hid = t * 32 + 16 * q + 8 * (e >> 2) + 4 * h + (e & 3);
+          av[e] = c32 < ME ? w2s[c32 * (MH + 8) + hid] : (__bf16)0.f;
+        }
+        zacc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, zacc, 0, 0, 0);
+      }
+    }
+    if (ok) {
+      float* z = a.Z + row * ME;
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const int e0 = 8 * g + 4 * h;
+        *(float4*)(z + e0) = make_float4(zacc[4 * g] + b2s[e0], zacc[4 * g + 1] + b2s[e0 + 1],
+                                         zacc[4 * g + 2] + b2s[e0 + 2], zacc[4 * g + 3] + b2s[e0 + 3]);
+      }
     }
   }
 }
@@ -424,6 +503,16 @@ hipError_t launch_fwd_t(const MlpArgs& a, hipStream_t s) {
 size_t mlp_wgrad_lds(int d) { return (size_t)(16 * (d + 4) + 2 * 16 * (MH + 4) + 16 * ME) * 4; }
 
 hipError_t launch_mlp_forward(const MlpArgs& a, bool train, hipStream_t s) {
+  if (a.bf16 && !train && !a.rows && a.d <= 128 && a.d % 16 == 0) {   // inference over the rows of X
+    const int64_t n_tiles = (a.R + 127) / 128;
+    if (n_tiles == 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<int64_t>(n_tiles, (int64_t)cu_count() * 2);
+    const int ns = a.d / 16;
+    if (ns <= 2) hipLaunchKernelGGL(k_mlp_embed<2>, dim3(grid), dim3(WG), 0, s, a, n_tiles);
+    else if (ns <= 4) hipLaunchKernelGGL(k_mlp_embed<4>, dim3(grid), dim3(WG), 0, s, a, n_tiles);
+    else hipLaunchKernelGGL(k_mlp_embed<8>, dim3(grid), dim3(WG), 0, s, a, n_tiles);
+    return hipGetLastError();
+  }
   if (a.bf16) return train ? launch_fwd_t<true, true>(a, s) : launch_fwd_t<true, false>(a, s);
   return train ? launch_fwd_t<false, true>(a, s) : launch_fwd_t<false, false>(a, s);
 }
