@@ -372,16 +372,19 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
         sq = __builtin_fmaf(v.x, v.x, __builtin_fmaf(v.y, v.y, __builtin_fmaf(v.z, v.z, v.w * v.w)));
       } else {
         bool in = e < TILE_F4 && kc + col < d;   // padded features stay exactly zero
-        float t0 = in ? bf16_round(v.x - S.mu[kc + col]) : 0.f;
-        float t1 = in ? bf16_round(v.y - S.mu[kc + col + 1]) : 0.f;
-        float t2 = in ? bf16_round(v.z - S.mu[kc + col + 2]) : 0.f;
-        float t3 = in ? bf16_round(v.w - S.mu[kc + col + 3]) : 0.f;
-        if (e < TILE_F4) {
-          __bf16* dst = &S.tile[buf].v[row * Tile::STRIDE + col];
-          dst[0] = (__bf16)t0;
-          dst[1] = (__bf16)t1;
-          dst[2] = (__bf16)t2;
-          dst[3] = (__bf16)t3;
+        // integer-key leaves are not centred (their mean is zero): no mean reads
+        const float4 m4 = ikey ? make_float4(0.f, 0.f, 0.f, 0.f)
+                               : make_float4(S.mu[kc + col], S.mu[kc + col + 1], S.mu[kc + col + 2], S.mu[kc + col + 3]);
+        float t0 = in ? bf16_round(v.x - m4.x) : 0.f;
+        float t1 = in ? bf16_round(v.y - m4.y) : 0.f;
+        float t2 = in ? bf16_round(v.z - m4.z) : 0.f;
+        float t3 = in ? bf16_round(v.w - m4.w) : 0.f;
+        if (e < TILE_F4) {   // the four halves in one 8-byte store
+          const uint32_t lo = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)t0) |
+                              ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)t1) << 16);
+          const uint32_t hi = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)t2) |
+                              ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)t3) << 16);
+          *(uint2*)&S.tile[buf].v[row * Tile::STRIDE + col] = make_uint2(lo, hi);
         }
         sq = __builtin_fmaf(t0, t0, __builtin_fmaf(t1, t1, __builtin_fmaf(t2, t2, t3 * t3)));
       }
