@@ -547,6 +547,124 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
   }
 }
 
+// Principal direction for d <= 16 (the learned division's embedding): one
+// wave per node, no workgroup barriers.  The sample (the positions, start
+// vector, iteration count and sign rule of k_pca_lds) sits in registers,
+// four rows per lane; butterfly sums give every lane the sample mean and the
+// centred sample's d x d scatter matrix Y^T Y, which goes through LDS so
+// that lane j keeps its row j; each power iteration v <- Y^T Y v / |Y^T Y v|
+// is then one row product per lane and a gather of the d results.
+constexpr int PCA_COV_DMAX = 16;
+
+__global__ __launch_bounds__(DIV_THREADS) void k_pca_cov(DivideLevelArgs a) {
+  if (a.skip && *a.skip) return;   // uniform: a later division of a stopped build
+  constexpr int D = PCA_COV_DMAX;
+  __shared__ float cov_s[DIV_THREADS / 64][D * D];
+  const int d = a.d;
+  const int lane = threadIdx.x & 63;
+  const int wpb = DIV_THREADS / 64;
+  const int64_t nw = (int64_t)gridDim.x * wpb;
+  auto wsum = [](float x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+  };
+  for (int64_t seg = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); seg < a.n_segs; seg += nw) {
+    const SegDesc sd = a.segs[seg];
+    const uint32_t m = sd.m;
+    const uint32_t s = m < 256 ? m : 256;
+    uint32_t wd = m / s;
+    if (wd < 1) wd = 1;
+    float y[4][D];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t i = (uint32_t)lane + 64u * r;
+      const bool in = i < s;
+      uint32_t row = 0;
+      if (in) {
+        const uint32_t pos = (uint32_t)(((uint64_t)i * m) / s) + (uint32_t)(rand64(a.seed, TAG_SAMPLE, sd.t, sd.v, i) % wd);
+        row = a.perm_in[(size_t)sd.slot * (size_t)a.n + sd.off + pos];
+      }
+      const float* xr = a.X + (size_t)row * d;
+#pragma unroll
+      for (int j4 = 0; j4 < D / 4; ++j4) {
+        const float4 v4 = (in && 4 * j4 < d) ? ((const float4*)xr)[j4] : make_float4(0.f, 0.f, 0.f, 0.f);
+        y[r][4 * j4] = v4.x;
+        y[r][4 * j4 + 1] = v4.y;
+        y[r][4 * j4 + 2] = v4.z;
+        y[r][4 * j4 + 3] = v4.w;
+      }
+    }
+    const float is = 1.0f / (float)s;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const float mu = wsum((y[0][j] + y[1][j]) + (y[2][j] + y[3][j])) * is;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if ((uint32_t)lane + 64u * r < s) y[r][j] -= mu;   // rows past the sample stay zero
+    }
+    // scatter matrix into LDS (both halves), then lane j keeps row j of it
+    float* Cs = cov_s[threadIdx.x >> 6];
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int l = j; l < D; ++l) {
+        float c = 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c = __builtin_fmaf(y[r][j], y[r][l], c);
+        c = wsum(c);
+        if (lane == 0) {
+          Cs[j * D + l] = c;
+          Cs[l * D + j] = c;
+        }
+      }
+    wave_sync();
+    float crow[D];
+#pragma unroll
+    for (int l = 0; l < D; ++l) crow[l] = Cs[(lane & (D - 1)) * D + l];
+    wave_sync();   // the next node overwrites Cs
+    float v[D];
+    float nn = 0.f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      v[j] = j < d ? rp_entry(a.seed, sd.t, sd.v, (uint32_t)j) : 0.f;
+      nn = __builtin_fmaf(v[j], v[j], nn);
+    }
+    const float inv0 = nn > 0.f ? 1.0f / sqrtf(nn) : 0.f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) v[j] *= inv0;
+    for (int itr = 0; itr < a.pca_iters; ++itr) {
+      // lane j forms (Y^T Y v)_j; every lane then gathers all of them
+      float acc = 0.f;
+#pragma unroll
+      for (int l = 0; l < D; ++l) acc = __builtin_fmaf(crow[l], v[l], acc);
+      float w[D];
+      float sq = 0.f;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        w[j] = __shfl(acc, j);
+        sq = __builtin_fmaf(w[j], w[j], sq);
+      }
+      if (sq > 0.f) {
+        const float iv = 1.0f / sqrtf(sq);
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = w[j] * iv;
+      }
+    }
+    // sign: the largest-magnitude entry positive, lowest index on ties
+    float best = -1.f, sg = 1.f;
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d && fabsf(v[j]) > best) {
+        best = fabsf(v[j]);
+        sg = v[j] < 0.f ? -1.f : 1.f;
+      }
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (lane == j && j < d) a.pca_dirs[(size_t)sd.dir_index * d + j] = sg * v[j];
+  }
+}
+
 // Principal direction for d > PCA_LDS_DMAX: the centred sample is read from
 // global memory (L2) in every iteration; same sample, start, iterations and
 // sign rule as k_pca_lds.
@@ -687,7 +805,10 @@ hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s) {
   if ((e = launch_fill_u32(a.hist, 0u, (size_t)a.n_segs * HIST_TOTAL, s)) != hipSuccess) return e;
   if (a.pca_iters > 0 && !a.dirs) {
     size_t base = (size_t)(2 * a.d + 256) * sizeof(float);
-    if (a.d <= PCA_LDS_DMAX) {
+    if (a.d <= PCA_COV_DMAX) {
+      const unsigned blocks = (unsigned)std::min<size_t>((a.n_segs + 3) / 4, (size_t)cu_count() * 8);
+      hipLaunchKernelGGL(k_pca_cov, dim3(blocks), dim3(DIV_THREADS), 0, s, a);
+    } else if (a.d <= PCA_LDS_DMAX) {
       const int cw = a.d / 4, G = DIV_THREADS / cw;
       const size_t tail = (2 * (size_t)a.d + 256 + (size_t)G * cw * 4) * sizeof(float);
       const size_t shm = (size_t)256 * (a.d + 4) * sizeof(float) + tail;
