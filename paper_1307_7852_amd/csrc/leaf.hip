@@ -91,7 +91,9 @@ __device__ __forceinline__ void list_insert_head(float (&L)[KP], float x) {
   static_assert(KI <= KP, "head longer than the list");
 #pragma unroll
   for (int j = KI - 1; j > 0; --j) L[j] = __builtin_amdgcn_fmed3f(L[j - 1], x, L[j]);
-  L[0] = fminf(L[0], x);
+  // keys are nonnegative floats, ordered as their bit patterns: an integer
+  // minimum needs no canonicalising of x
+  L[0] = __uint_as_float(min(__float_as_uint(L[0]), __float_as_uint(x)));
 }
 
 // Eight canonical distances: two query rows, four candidates each (dist2_g16's arithmetic per pair).
@@ -335,6 +337,29 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
   const int ntile = (m + TILE - 1) / TILE;
   const int nsteps = ntile * nchunk;
 
+  // Integer keys straight from the Gram (FP32 integer data, one chunk,
+  // leaves of at most 512): with the query scaled by -2 and the accumulator
+  // starting at 2^23 + |x_c|^2 + M (M: the leaf's largest member norm), the
+  // Gram ends at 2^23 + D', where D' = D - |x_q|^2 + M is an integer in
+  // [0, 4M] that ranks the lane's candidates as D does.  Every partial sum
+  // is an integer in (2^22, 2^24), so all of it is exact, and the float's
+  // bits are 0x4B000000 + D'.  With 4M below FK_DSAT, D' shifted above a
+  // 9-bit position stays below KEY_NONE and the exponent shifts out, so one
+  // funnel shift of (bits, position << 23) by 23 forms the key.  The true
+  // distance D' + |x_q|^2 - M is restored for the k written entries.
+  constexpr uint32_t FK_BITS = 9u;
+  constexpr uint32_t FK_DSAT = (KEY_NONE >> FK_BITS) - 1u;   // (FK_DSAT << 9) | 511 < KEY_NONE
+  bool fastkey = false;
+  if constexpr (!BF16) {
+    const float mxn = __uint_as_float(S.max_n);
+    fastkey = ikey && nchunk == 1 && m <= (1 << FK_BITS) && 4.0f * mxn < (float)FK_DSAT;   // uniform
+    if (fastkey) {
+      const float off = mxn + 8388608.0f;
+      for (int i = tid; i < m; i += C::THREADS) S.nrm[i] += off;   // padding rows keep PAD_NORM
+      __syncthreads();
+    }
+  }
+
   // global -> registers for step st (tile st / nchunk, chunk st % nchunk).
   // Every thread issues all STAGE_F4 loads unconditionally, so the number of
   // loads in flight is fixed and the Gram's MFMAs need not wait for this
@@ -466,6 +491,17 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
       }
       nq += __shfl_xor(nq, 32);
       if (h == 0) S.qn[w][r32] = nq;
+      if constexpr (!BF16) {
+        if (fastkey) {
+#pragma unroll
+          for (int i = 0; i < QFrag<KC, BF16>::N4; ++i) {
+            qf.f[i].x *= -2.0f;
+            qf.f[i].y *= -2.0f;
+            qf.f[i].z *= -2.0f;
+            qf.f[i].w *= -2.0f;
+          }
+        }
+      }
     }
     float Lk[KP];
 #pragma unroll
@@ -504,21 +540,52 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
         stage_load(nxt, rg);
       }
       if (wave_on) {
-        if (kci == 0) {
-#pragma unroll
-          for (int r = 0; r < 16; ++r) { acc0[r] = 0.f; acc1[r] = 0.f; }
-        }
         if constexpr (!BF16) {
+          // one accumulation chain (back-to-back dependent MFMAs of one shape
+          // need no wait); a chunk that starts a tile starts from the zero
+          // constant, so the accumulator needs no clearing
           const float4* trow = reinterpret_cast<const float4*>(&S.tile[buf].v[r32 * Tile::STRIDE + h * HALF]);
+          // the tile's next 16 bytes are read while the current ones feed MFMAs
+          auto chain = [&](int i0) __attribute__((always_inline)) {
+            float4 nx = trow[i0];
 #pragma unroll
-          for (int i = 0; i < HALF / 4; ++i) {
-            float4 cv = trow[i];
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.x, qf.f[i].x, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.y, qf.f[i].y, acc1, 0, 0, 0);
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.z, qf.f[i].z, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.w, qf.f[i].w, acc1, 0, 0, 0);
+            for (int i = 0; i < HALF / 4; ++i) {
+              if (i < i0) continue;
+              const float4 cv = nx;
+              if (i + 1 < HALF / 4) nx = trow[i + 1];
+              acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.x, qf.f[i].x, acc0, 0, 0, 0);
+              acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.y, qf.f[i].y, acc0, 0, 0, 0);
+              acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.z, qf.f[i].z, acc0, 0, 0, 0);
+              acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.w, qf.f[i].w, acc0, 0, 0, 0);
+            }
+          };
+          if (fastkey) {
+            // register r: candidate c0 + 8(r/4) + 4h + r%4, as the keys read it
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+              const float4 n = *reinterpret_cast<const float4*>(&S.nrm[c0 + 8 * g + 4 * h]);
+              acc0[4 * g] = n.x;
+              acc0[4 * g + 1] = n.y;
+              acc0[4 * g + 2] = n.z;
+              acc0[4 * g + 3] = n.w;
+            }
+            chain(0);
+          } else if (kci == 0) {
+            const float4 cv = trow[0];
+            const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.x, qf.f[0].x, zero, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.y, qf.f[0].y, acc0, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.z, qf.f[0].z, acc0, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(cv.w, qf.f[0].w, acc0, 0, 0, 0);
+            chain(1);
+          } else {
+            chain(0);
           }
         } else {
+          if (kci == 0) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) { acc0[r] = 0.f; acc1[r] = 0.f; }
+          }
           const bf16x8* trow = reinterpret_cast<const bf16x8*>(&S.tile[buf].v[r32 * Tile::STRIDE + h * HALF]);
 #pragma unroll
           for (int i = 0; i < HALF / 8; ++i) {
@@ -537,17 +604,26 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
           const bool ragged = c0 + TILE > m;  // uniform: the last tile has padding rows
           // EXACT: integer keys; EDGE: the tile needs the self-pair or padding
           // masks; KI: list entries kept (integer keys need only the k smallest:
-          // KP/2, 5KP/8, 3KP/4 or KP, the first that holds k)
-          auto insert_tile = [&](auto exact_tag, auto edge_tag, auto len_tag) {
+          // KP/2, 5KP/8, 3KP/4 or KP, the first that holds k); FAST: keys from
+          // the Gram's bits, their position without the lane half 4h (bit 2,
+          // set before the halves merge)
+          auto insert_tile = [&](auto exact_tag, auto edge_tag, auto len_tag, auto fast_tag) {
             constexpr bool EXACT = decltype(exact_tag)::value;
             constexpr bool EDGE = decltype(edge_tag)::value;
             constexpr int KI = decltype(len_tag)::value;
+            constexpr bool FAST = decltype(fast_tag)::value;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
               const int cl = 8 * (r >> 2) + (r & 3);
-              const float nc = (r & 3) == 0 ? n4[r >> 2].x : (r & 3) == 1 ? n4[r >> 2].y : (r & 3) == 2 ? n4[r >> 2].z : n4[r >> 2].w;
-              const float dv = __builtin_fmaf(-2.0f, acc0[r] + acc1[r], nq + nc);
-              float x = EXACT ? make_ikey(dv, pbase + (uint32_t)cl) : make_key(dv, pbase + (uint32_t)cl);
+              float x;
+              if constexpr (FAST) {
+                // (bits << 9) | position; padding rows (ragged tile) are masked below
+                x = __uint_as_float(__builtin_amdgcn_alignbit(__float_as_uint(acc0[r]), (uint32_t)(c0 + cl) << 23, 23u));
+              } else {
+                const float nc = (r & 3) == 0 ? n4[r >> 2].x : (r & 3) == 1 ? n4[r >> 2].y : (r & 3) == 2 ? n4[r >> 2].z : n4[r >> 2].w;
+                const float dv = __builtin_fmaf(-2.0f, BF16 ? acc0[r] + acc1[r] : acc0[r], nq + nc);
+                x = EXACT ? make_ikey(dv, pbase + (uint32_t)cl) : make_key(dv, pbase + (uint32_t)cl);
+              }
               if constexpr (EDGE) {
                 if (diag && (cl + 4 * h == r32)) x = __uint_as_float(KEY_NONE);
                 if (EXACT && ragged && (int)pbase + cl >= m) x = __uint_as_float(KEY_NONE);
@@ -561,19 +637,24 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
           using KHalf = std::integral_constant<int, KP / 2>;
           using K58 = std::integral_constant<int, KP / 2 + KP / 8>;
           using K3q = std::integral_constant<int, KP - KP / 4>;
-          if (ikey) {
+          auto tiers = [&](auto fast_tag) {
             const bool edge = diag || ragged;
             if (k <= KP / 2) {
-              if (edge) insert_tile(T_{}, T_{}, KHalf{}); else insert_tile(T_{}, F_{}, KHalf{});
+              if (edge) insert_tile(T_{}, T_{}, KHalf{}, fast_tag); else insert_tile(T_{}, F_{}, KHalf{}, fast_tag);
             } else if (k <= KP / 2 + KP / 8) {
-              if (edge) insert_tile(T_{}, T_{}, K58{}); else insert_tile(T_{}, F_{}, K58{});
+              if (edge) insert_tile(T_{}, T_{}, K58{}, fast_tag); else insert_tile(T_{}, F_{}, K58{}, fast_tag);
             } else if (k <= KP - KP / 4) {
-              if (edge) insert_tile(T_{}, T_{}, K3q{}); else insert_tile(T_{}, F_{}, K3q{});
+              if (edge) insert_tile(T_{}, T_{}, K3q{}, fast_tag); else insert_tile(T_{}, F_{}, K3q{}, fast_tag);
             } else {
-              if (edge) insert_tile(T_{}, T_{}, KFull{}); else insert_tile(T_{}, F_{}, KFull{});
+              if (edge) insert_tile(T_{}, T_{}, KFull{}, fast_tag); else insert_tile(T_{}, F_{}, KFull{}, fast_tag);
             }
+          };
+          if (!BF16 && fastkey) {
+            tiers(std::integral_constant<bool, !BF16>{});
+          } else if (ikey) {
+            tiers(F_{});
           } else {
-            if (diag) insert_tile(F_{}, T_{}, KFull{}); else insert_tile(F_{}, F_{}, KFull{});
+            if (diag) insert_tile(F_{}, T_{}, KFull{}, F_{}); else insert_tile(F_{}, F_{}, KFull{}, F_{});
           }
         }
       }
@@ -591,6 +672,10 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     if (!wave_on) continue;                   // no barrier below this point
     // ---- merge the two half-lists of each query: the KP smallest of both
     {
+      if (fastkey && h) {   // the lane half's position bit (KEY_NONE has it set already)
+#pragma unroll
+        for (int j = 0; j < KP; ++j) Lk[j] = __uint_as_float(__float_as_uint(Lk[j]) | 4u);
+      }
       float P[KP];
 #pragma unroll
       for (int j = 0; j < KP; ++j) P[j] = __shfl_xor(Lk[j], 32);
@@ -618,14 +703,19 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
           // Rows of leaves with at most k members have padding at slot k - 1,
           // so the check covers every written slot, not only the k-th.
           bool sat = false;
+          // fast keys: D' in the bits above pbits, D = D' + |x_q|^2 - M (exact)
+          const uint32_t psh = fastkey ? FK_BITS : 11u;
+          const uint32_t pmask = (1u << psh) - 1u;
+          const uint32_t dsat = fastkey ? FK_DSAT : KEY_DSAT;
+          const float dshift = fastkey ? nq - __uint_as_float(S.max_n) : 0.f;
 #pragma unroll
           for (int j = 0; j < KP; ++j) {
             const uint32_t kk = __float_as_uint(Lk[j]);
             const bool none = kk == KEY_NONE;
-            if (j < k) sat = sat || (!none && (kk >> 11) >= KEY_DSAT);
+            if (j < k) sat = sat || (!none && (kk >> psh) >= dsat);
             if (j < k && (j & 1) == h) {
-              ids_out[(size_t)qid * a.list_row + j] = none ? KNNG_NONE : S.ids[kk & POS_MASK];
-              dist_out[(size_t)qid * a.list_row + j] = none ? INF : (float)(kk >> 11);
+              ids_out[(size_t)qid * a.list_row + j] = none ? KNNG_NONE : S.ids[kk & pmask];
+              dist_out[(size_t)qid * a.list_row + j] = none ? INF : (float)(kk >> psh) + dshift;
             }
           }
           if (sat && h == 0) {
