@@ -258,11 +258,11 @@ __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
   const int g = lane >> 4, gl = lane & 15;
   const float* xp = a.X + (size_t)p * d;
   // Byte rows (every value of X an integer in 0..255, d <= 256 and a
-  // multiple of 8): every partial sum of a squared distance is an integer
-  // below 2^24, so any summation order gives dist2_g16's value exactly.  A
-  // lane then holds 8 consecutive values of p (block gl, and gl + 16 when
-  // d > 128) and reads one 8-byte piece of each candidate row: eight rows per
-  // lane group are in flight.
+  // multiple of 8): the squared distance is an integer below 2^24, formed in
+  // integers as |x|^2 + |y|^2 - 2 x.y with four-byte dot products, so it is
+  // exactly dist2_g16's value.  A lane holds 8 consecutive bytes of p (block
+  // gl, and gl + 16 when d > 128) and reads one 8-byte piece of each
+  // candidate row: eight rows per lane group are in flight.
   // NB 8-value blocks per lane: one up to d = 128 (NCH <= 2), two up to 256
   constexpr int NB = NCH >= 3 ? 2 : 1;
   const bool u8 = NCH >= 1 && NCH <= 4 && a.X8 && (a.diag->exact_flags & EXACT_U8) != 0u && (d & 7) == 0 &&
@@ -270,17 +270,13 @@ __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
   if (u8) {
     constexpr int R8 = 8;
     const int nb = d >> 3;
-    float xq[NB][8];
+    uint2 xw[NB];
+    uint32_t x2[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int blk = gl + 16 * b;
-      uint2 v = make_uint2(0u, 0u);
-      if (blk < nb) v = *(const uint2*)(a.X8 + (size_t)p * d + 8 * blk);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        xq[b][e] = (float)((v.x >> (8 * e)) & 0xFFu);
-        xq[b][4 + e] = (float)((v.y >> (8 * e)) & 0xFFu);
-      }
+      xw[b] = blk < nb ? *(const uint2*)(a.X8 + (size_t)p * d + 8 * blk) : make_uint2(0u, 0u);
+      x2[b] = __builtin_amdgcn_udot4(xw[b].x, xw[b].x, __builtin_amdgcn_udot4(xw[b].y, xw[b].y, 0u, false), false);
     }
     for (int base = 0; base < U; base += 4 * R8) {
       // every lane loads (lanes past the row read block 0 and drop the sum
@@ -299,25 +295,23 @@ __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
       }
 #pragma unroll
       for (int j = 0; j < R8; ++j) {
-        float acc = 0.f;
+        uint32_t acc = 0u;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          float part = 0.f;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float y0 = (float)((wr[j][b].x >> (8 * e)) & 0xFFu), y1 = (float)((wr[j][b].y >> (8 * e)) & 0xFFu);
-            const float e0 = xq[b][e] - y0, e1 = xq[b][4 + e] - y1;
-            part = __builtin_fmaf(e0, e0, part);
-            part = __builtin_fmaf(e1, e1, part);
-          }
-          acc += gl + 16 * b < nb ? part : 0.f;
+          const uint2 y = wr[j][b];
+          const uint32_t yy = __builtin_amdgcn_udot4(y.x, y.x, __builtin_amdgcn_udot4(y.y, y.y, 0u, false), false);
+          const uint32_t xy = __builtin_amdgcn_udot4(xw[b].x, y.x, __builtin_amdgcn_udot4(xw[b].y, y.y, 0u, false), false);
+          // the block's sum of (x - y)^2: nonnegative, so the unsigned
+          // arithmetic wraps back to it
+          const uint32_t part = x2[b] + yy - 2u * xy;
+          acc += gl + 16 * b < nb ? part : 0u;
         }
         acc += __shfl_xor(acc, 8, 16);
         acc += __shfl_xor(acc, 4, 16);
         acc += __shfl_xor(acc, 2, 16);
         acc += __shfl_xor(acc, 1, 16);
         const int ci = base + g + 4 * j;
-        if (gl == 0 && ci < U) cd_s[w][ci] = acc;
+        if (gl == 0 && ci < U) cd_s[w][ci] = (float)acc;
       }
     }
   } else if constexpr (NCH > 0) {
@@ -620,19 +614,15 @@ __global__ __launch_bounds__(256) void k_prop_queue(PropArgs a, int qcap, int lo
   const bool u8 = NCH >= 1 && NCH <= 4 && a.X8 && (a.diag->exact_flags & EXACT_U8) != 0u && (d & 7) == 0 &&
                   d <= 128 * NB;   // uniform
   const int nblk = d >> 3;
-  float xq[NB][8];
+  uint2 xw[NB];
+  uint32_t x2[NB];
   float4 xr[NCH > 0 ? NCH : 1];
   if (u8) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int blk = gl + 16 * b;
-      uint2 v = make_uint2(0u, 0u);
-      if (blk < nblk) v = *(const uint2*)(a.X8 + (size_t)p * d + 8 * blk);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        xq[b][e] = (float)((v.x >> (8 * e)) & 0xFFu);
-        xq[b][4 + e] = (float)((v.y >> (8 * e)) & 0xFFu);
-      }
+      xw[b] = blk < nblk ? *(const uint2*)(a.X8 + (size_t)p * d + 8 * blk) : make_uint2(0u, 0u);
+      x2[b] = __builtin_amdgcn_udot4(xw[b].x, xw[b].x, __builtin_amdgcn_udot4(xw[b].y, xw[b].y, 0u, false), false);
     }
   } else if constexpr (NCH > 0) {
 #pragma unroll
@@ -661,25 +651,21 @@ __global__ __launch_bounds__(256) void k_prop_queue(PropArgs a, int qcap, int lo
         }
 #pragma unroll
         for (int j = 0; j < R8; ++j) {
-          float acc = 0.f;
+          uint32_t acc = 0u;   // |x|^2 + |y|^2 - 2 x.y per block, as in k_prop_forward
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
-            float part = 0.f;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const float y0 = (float)((wr[j][b].x >> (8 * e)) & 0xFFu), y1 = (float)((wr[j][b].y >> (8 * e)) & 0xFFu);
-              const float e0 = xq[b][e] - y0, e1 = xq[b][4 + e] - y1;
-              part = __builtin_fmaf(e0, e0, part);
-              part = __builtin_fmaf(e1, e1, part);
-            }
-            acc += gl + 16 * b < nblk ? part : 0.f;
+            const uint2 y = wr[j][b];
+            const uint32_t yy = __builtin_amdgcn_udot4(y.x, y.x, __builtin_amdgcn_udot4(y.y, y.y, 0u, false), false);
+            const uint32_t xy = __builtin_amdgcn_udot4(xw[b].x, y.x, __builtin_amdgcn_udot4(xw[b].y, y.y, 0u, false), false);
+            const uint32_t part = x2[b] + yy - 2u * xy;
+            acc += gl + 16 * b < nblk ? part : 0u;
           }
           acc += __shfl_xor(acc, 8, 16);
           acc += __shfl_xor(acc, 4, 16);
           acc += __shfl_xor(acc, 2, 16);
           acc += __shfl_xor(acc, 1, 16);
           const int ci = base + g + 4 * j;
-          if (gl == 0 && ci < cnt) Q[b0 + ci] = pack_did(acc, (uint32_t)Q[b0 + ci]);
+          if (gl == 0 && ci < cnt) Q[b0 + ci] = pack_did((float)acc, (uint32_t)Q[b0 + ci]);
         }
       }
     } else if constexpr (NCH > 0) {

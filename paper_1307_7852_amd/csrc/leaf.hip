@@ -41,6 +41,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int QPW = 32;            // queries per wave
 constexpr int TILE = 32;           // candidates per tile
 constexpr int TILE_BUFS = 4;       // tile buffers in LDS: staged two steps ahead, a barrier every second step
+static_assert((TILE_BUFS & (TILE_BUFS - 1)) == 0, "buffer rotation is a mask");
 constexpr int MU_MAX = 2048;       // BF16 path: d <= 2048
 constexpr uint32_t POS_MASK = 0x7FFu;          // position bits of a key (leaf <= 2048)
 constexpr uint32_t KEY_NONE = 0x7F7FFFFFu;     // FLT_MAX: above every key
@@ -336,9 +337,14 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
   const int nchunk = (d + KC - 1) / KC;
   const int ntile = (m + TILE - 1) / TILE;
   const int nsteps = ntile * nchunk;
+  // st / nchunk as a multiply-high by M = ceil(2^32 / nchunk): exact for
+  // st < 2^32 / nchunk, far above any step count here
+  const uint32_t nch_m = nchunk == 1 ? 0u : (uint32_t)((0x100000000ull + (uint64_t)nchunk - 1u) / (uint64_t)nchunk);
+  auto step_tile = [&](int st) -> int { return nchunk == 1 ? st : (int)__umulhi((uint32_t)st, nch_m); };
 
-  // Integer keys straight from the Gram (FP32 integer data, one chunk,
-  // leaves of at most 512): with the query scaled by -2 and the accumulator
+  // Integer keys straight from the Gram (integer data, exact in the Gram's
+  // input type, one chunk, leaves of at most 512; in BF16 such leaves are
+  // not centred): with the query scaled by -2 and the accumulator
   // starting at 2^23 + |x_c|^2 + M (M: the leaf's largest member norm), the
   // Gram ends at 2^23 + D', where D' = D - |x_q|^2 + M is an integer in
   // [0, 4M] that ranks the lane's candidates as D does.  Every partial sum
@@ -350,7 +356,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
   constexpr uint32_t FK_BITS = 9u;
   constexpr uint32_t FK_DSAT = (KEY_NONE >> FK_BITS) - 1u;   // (FK_DSAT << 9) | 511 < KEY_NONE
   bool fastkey = false;
-  if constexpr (!BF16) {
+  {
     const float mxn = __uint_as_float(S.max_n);
     fastkey = ikey && nchunk == 1 && m <= (1 << FK_BITS) && 4.0f * mxn < (float)FK_DSAT;   // uniform
     if (fastkey) {
@@ -368,7 +374,8 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
   // multiply, not a select, which the compiler would turn into a branch
   // around the load.
   auto stage_load = [&](int st, float4 (&rg)[STAGE_F4]) {
-    int c0 = (st / nchunk) * TILE, kc = (st % nchunk) * KC;
+    const int t = step_tile(st);
+    int c0 = t * TILE, kc = (st - t * nchunk) * KC;
 #pragma unroll
     for (int u = 0; u < STAGE_F4; ++u) {
       int e = tid + u * C::THREADS;
@@ -385,7 +392,8 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
   // member norms (rows of a tile are held by F4_PER_ROW consecutive lanes,
   // reduced by shuffles)
   auto stage_store = [&](int st, int buf, const float4 (&rg)[STAGE_F4], bool norms) {
-    int c0 = (st / nchunk) * TILE, kci = st % nchunk, kc = kci * KC;
+    const int t = step_tile(st);
+    int c0 = t * TILE, kci = st - t * nchunk, kc = kci * KC;
 #pragma unroll
     for (int u = 0; u < STAGE_F4; ++u) {
       int e = tid + u * C::THREADS;
@@ -491,8 +499,8 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
       }
       nq += __shfl_xor(nq, 32);
       if (h == 0) S.qn[w][r32] = nq;
-      if constexpr (!BF16) {
-        if (fastkey) {
+      if (fastkey) {   // scaling by -2 is exact in either type
+        if constexpr (!BF16) {
 #pragma unroll
           for (int i = 0; i < QFrag<KC, BF16>::N4; ++i) {
             qf.f[i].x *= -2.0f;
@@ -500,6 +508,11 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
             qf.f[i].z *= -2.0f;
             qf.f[i].w *= -2.0f;
           }
+        } else {
+#pragma unroll
+          for (int i = 0; i < QFrag<KC, BF16>::N8; ++i)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) qf.b[i][e] = (__bf16)(-2.0f * (float)qf.b[i][e]);
         }
       }
     }
@@ -511,14 +524,15 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
       for (int s0 = 0; s0 < 2 && s0 < nsteps; ++s0) {
         float4 rg[STAGE_F4];
         stage_load(s0, rg);
-        stage_store(s0, (s0 + bufbase) % TILE_BUFS, rg, first && !pre_norms);
+        stage_store(s0, (s0 + bufbase) & (TILE_BUFS - 1), rg, first && !pre_norms);
       }
       if constexpr (DEEP) stage_load(2 < nsteps ? 2 : 0, pend);   // the tile step 0 stores
     }
     __syncthreads();
     for (int st = 0; st < nsteps; ++st) {
-      const int buf = (st + bufbase) % TILE_BUFS;
-      const int c0 = (st / nchunk) * TILE, kci = st % nchunk;
+      const int buf = (st + bufbase) & (TILE_BUFS - 1);
+      const int tl = step_tile(st);
+      const int c0 = tl * TILE, kci = st - tl * nchunk;
       // the query chunk is loaded before the next tile's prefetch so that the
       // MFMAs wait only for the older loads and the prefetch stays in flight
       if (wave_on && nchunk > 1) qf.load(qrow, kci * KC, d, h, S.mu, qok);
@@ -582,16 +596,29 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
             chain(0);
           }
         } else {
-          if (kci == 0) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) { acc0[r] = 0.f; acc1[r] = 0.f; }
-          }
           const bf16x8* trow = reinterpret_cast<const bf16x8*>(&S.tile[buf].v[r32 * Tile::STRIDE + h * HALF]);
+          if (fastkey) {   // one chain from the norms, as in the FP32 form
 #pragma unroll
-          for (int i = 0; i < HALF / 8; ++i) {
-            bf16x8 cv = trow[i];
-            if (i % 2 == 0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cv, qf.b[i], acc0, 0, 0, 0);
-            else acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cv, qf.b[i], acc1, 0, 0, 0);
+            for (int g = 0; g < 4; ++g) {
+              const float4 n = *reinterpret_cast<const float4*>(&S.nrm[c0 + 8 * g + 4 * h]);
+              acc0[4 * g] = n.x;
+              acc0[4 * g + 1] = n.y;
+              acc0[4 * g + 2] = n.z;
+              acc0[4 * g + 3] = n.w;
+            }
+#pragma unroll
+            for (int i = 0; i < HALF / 8; ++i) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(trow[i], qf.b[i], acc0, 0, 0, 0);
+          } else {
+            if (kci == 0) {
+#pragma unroll
+              for (int r = 0; r < 16; ++r) { acc0[r] = 0.f; acc1[r] = 0.f; }
+            }
+#pragma unroll
+            for (int i = 0; i < HALF / 8; ++i) {
+              bf16x8 cv = trow[i];
+              if (i % 2 == 0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cv, qf.b[i], acc0, 0, 0, 0);
+              else acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cv, qf.b[i], acc1, 0, 0, 0);
+            }
           }
         }
         if (kci == nchunk - 1) {
@@ -649,8 +676,8 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
               if (edge) insert_tile(T_{}, T_{}, KFull{}, fast_tag); else insert_tile(T_{}, F_{}, KFull{}, fast_tag);
             }
           };
-          if (!BF16 && fastkey) {
-            tiers(std::integral_constant<bool, !BF16>{});
+          if (fastkey) {
+            tiers(T_{});
           } else if (ikey) {
             tiers(F_{});
           } else {
@@ -659,16 +686,16 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
         }
       }
       if constexpr (DEEP) {
-        stage_store(nxt, (ahead + bufbase) % TILE_BUFS, pend, first && more && !pre_norms);
+        stage_store(nxt, (ahead + bufbase) & (TILE_BUFS - 1), pend, first && more && !pre_norms);
 #pragma unroll
         for (int u = 0; u < STAGE_F4; ++u) pend[u] = rg[u];
       } else {
-        stage_store(nxt, (ahead + bufbase) % TILE_BUFS, rg, first && more && !pre_norms);
+        stage_store(nxt, (ahead + bufbase) & (TILE_BUFS - 1), rg, first && more && !pre_norms);
       }
       if ((st & 1) || st + 1 == nsteps) __syncthreads();
     }
     staged = follow && nsteps >= 2;
-    bufbase = (nsteps + bufbase) % TILE_BUFS;   // the buffer of the next pass's step 0
+    bufbase = (nsteps + bufbase) & (TILE_BUFS - 1);   // the buffer of the next pass's step 0
     if (!wave_on) continue;                   // no barrier below this point
     // ---- merge the two half-lists of each query: the KP smallest of both
     {
