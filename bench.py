@@ -319,8 +319,8 @@ def main():
                          "the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
-              f"(the multi-GPU sharding is a design in DESIGN.md, not code).", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              f"(one process drives one GPU; sharding over several is not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -64,7 +64,7 @@ typedef enum {
   KNNG_EINVAL = -1,      /* invalid argument or parameter                      */
   KNNG_ENOMEM = -2,      /* workspace smaller than knng_workspace_bytes()      */
   KNNG_EHIP = -3,        /* a HIP runtime call failed                          */
-  KNNG_EUNSUPPORTED = -4 /* valid but not supported by this build              */
+  KNNG_EUNSUPPORTED = -4 /* valid but not supported by the library            */
 } knng_status;
 
 typedef enum {

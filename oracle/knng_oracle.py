@@ -20,7 +20,7 @@ Plain, slow and written to be checked against the paper by eye:
     first-order, round-synchronous reading, with the pairwise updating of
     Section 3.4.
 
-Readings where the paper is silent (each listed in the design doc):
+Readings where the paper is silent:
   R1  a node is split while it holds more than `leaf_max` points (the paper's
       "until smaller than g" with g = leaf_max + 1);
   R2  ties are broken by point id everywhere: points are ordered by
