@@ -11,6 +11,7 @@ one (with its recall-judged fallback), a (T, rounds) sweep and the CPU oracle
 timed on a bounded sample.
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -170,10 +171,13 @@ def time_builds(torch, K, kp, X_t, steps, warmup, S=None, embed=None):
             e0.record()
             embed()
             e1.record()
+        if S is not None:   # divisions on the rows of S
             st = K.build_split(kp, X_t, S, ids, dist, ws, timed=True)
+        else:
+            st = K.build_timed(kp, X_t, ids, dist, ws)
+        if embed is not None:
             st["embed"] = e0.elapsed_time(e1)
-            return st
-        return K.build_timed(kp, X_t, ids, dist, ws)
+        return st
 
     for i in range(warmup):
         step()
@@ -198,6 +202,10 @@ def stage_means(stages):
     return {k: round(v, 3) for k, v in out.items()}
 
 
+# the learned form measured beside each plain workload that has one
+LEARNED_FORM = {"sift1m": "sift1m_learned_bf16", "sift4m": "sift4m_learned"}
+
+
 def train_partitioner(K, torch, dev, steps, X1_t):
     """The learned division's network, trained on the graph the plain method
     builds for the 1M SIFT-like workload (training time is reported, not
@@ -218,26 +226,35 @@ def train_partitioner(K, torch, dev, steps, X1_t):
                   "graph": "sift1m plain build (principal-direction divisions, T=8, 3 rounds)"}
 
 
-def learned_form(torch, K, X, X_t, args, plain_value):
-    """The BF16 + learned-partitioner form on the same data, with its
-    fallback rule: the learned division is kept only if its recall@10 on
-    held-out queries (exact k-NN as judge) is at least that of the plain
-    method's own division (principal directions) in the same settings."""
-    w = datagen.WORKLOADS["sift1m_learned_bf16"]
+def learned_form(torch, K, X, X_t, args, plain_value, plain_w, queries=None, kth=None, grid=None):
+    """The learned-partitioner form on the same data (BF16 leaf Gram for the
+    1M workload), with its fallback rule: the learned division is kept only
+    if its recall@10 on held-out queries (exact k-NN as judge) is at least
+    that of the plain workload's own division in the same settings.  The
+    network is always trained on the 1M workload's plain graph; with `grid`,
+    both forms are also swept over (T, rounds)."""
+    w = datagen.WORKLOADS[LEARNED_FORM[plain_w.name]]
     dev = X_t.device
-    part, train_info = train_partitioner(K, torch, dev, args.train_steps, X_t)
+    if plain_w.name == "sift1m":
+        part, train_info = train_partitioner(K, torch, dev, args.train_steps, X_t)
+    else:
+        log("  training data: the 1M workload")
+        X1_t = torch.from_numpy(datagen.make(datagen.WORKLOADS["sift1m"])).to(dev)
+        part, train_info = train_partitioner(K, torch, dev, args.train_steps, X1_t)
+        del X1_t
     Z = part.embed(X_t)
     torch.cuda.synchronize()
     held = datagen.query_sample(w.n, 2000, w.seed + 77)
     kth_h = exact_kth(torch, X_t, held, 10)
     kp_l = make_params(K, w)
+    w_p = dataclasses.replace(w, split=plain_w.split)   # the plain division, same T, rounds and Gram
+    kp_p = make_params(K, w_p)
     ws = K.alloc_workspace(kp_l, K.OP_BUILD, dev)
     ids = torch.empty((w.n, w.k), dtype=torch.int32, device=dev)
     dist = torch.empty((w.n, w.k), dtype=torch.float32, device=dev)
     K.build_split(kp_l, X_t, Z, ids, dist, ws)
     torch.cuda.synchronize()
     r_learned = recall_at(X, ids.cpu().numpy(), held, kth_h, 10)
-    kp_p = make_params(K, w)   # same T, rounds and BF16 Gram; the plain method's division on X
     K.build(kp_p, X_t, ids, dist, ws)
     torch.cuda.synchronize()
     r_plain = recall_at(X, ids.cpu().numpy(), held, kth_h, 10)
@@ -252,16 +269,32 @@ def learned_form(torch, K, X, X_t, args, plain_value):
     else:
         ms, stages, ids, dist, _ = time_builds(torch, K, kp_p, X_t, args.steps, args.warmup)
     ids_h = ids.cpu().numpy()
+    del ids, dist
     value = w.n / (ms * 1e-3)
-    return {"workload": w.name, "T": w.T, "rounds": w.rounds, "leaf_gram": "bf16", "rerank_m": w.rerank_m,
-            "division": "learned (principal direction of the 16-d embedding)" if use else "plain (fallback)",
-            "points_per_s": round(value, 1), "ms_per_step": round(ms, 3),
-            "speedup_vs_plain": round(value / plain_value, 3),
-            "stages_ms_per_step": stage_means(stages),
-            "fallback_rule": {"judge": "recall@10 on 2000 held-out queries against exact k-NN",
-                              "recall_learned": round(r_learned, 5), "recall_plain_division": round(r_plain, 5),
-                              "use_learned": bool(use)},
-            "training": train_info}, ids_h
+    out = {"workload": w.name, "T": w.T, "rounds": w.rounds, "leaf_gram": w.precision, "rerank_m": w.rerank_m,
+           "division": "learned (principal direction of the 16-d embedding)" if use else f"plain ({plain_w.split}, fallback)",
+           "points_per_s": round(value, 1), "ms_per_step": round(ms, 3),
+           "speedup_vs_plain": round(value / plain_value, 3),
+           "stages_ms_per_step": stage_means(stages),
+           "fallback_rule": {"judge": "recall@10 on 2000 held-out queries against exact k-NN",
+                             "plain_division": plain_w.split,
+                             "recall_learned": round(r_learned, 5), "recall_plain_division": round(r_plain, 5),
+                             "use_learned": bool(use)},
+           "training": train_info}
+    if grid is not None:
+        rows = []
+        for T in grid[0]:
+            for r in grid[1]:
+                kp = make_params(K, w, T=T, rounds=r)
+                ms_g, _, ids_g, _, _ = time_builds(torch, K, kp, X_t, 2, 1, S=Z)
+                rec = recall_at(X, ids_g.cpu().numpy(), queries, kth, 10)
+                rows.append({"T": T, "rounds": r, "ms": round(ms_g, 3), "recall@10": round(rec, 5)})
+                log(f"  learned sweep T={T} rounds={r}: {ms_g:.2f} ms recall {rec:.4f}")
+                del ids_g
+        ok = [x for x in rows if x["recall@10"] >= 0.95]
+        out["sweep"] = {"grid": rows, "cheapest_at_0.95": min(ok, key=lambda x: x["ms"]) if ok else None,
+                        "ms_excludes": "the embedding pass (once per data set)"}
+    return out, ids_h
 
 
 def sweep(torch, K, w, X, X_t, queries, kth, Ts, rounds_list):
@@ -480,16 +513,19 @@ def main():
         out["graph_ms_per_step"] = round(graph_ms, 3)
     if tiles is not None:
         out["leaf_tiles"] = tiles
-    do_learned = args.learned == "on" or (args.learned == "auto" and w.name == "sift1m")
-    if do_learned:
-        log("learned BF16 form")
-        out["learned_bf16"], ids_l = learned_form(torch, K, X, X_t, args, value)
-        out["learned_bf16"]["recall@10"] = round(recall_at(X, ids_l, queries, kth, 10), 5)
-        log(f"  {out['learned_bf16']['points_per_s']:.0f} points/s, recall {out['learned_bf16']['recall@10']}")
+    do_learned = w.name in LEARNED_FORM and (args.learned == "on" or (args.learned == "auto" and w.name == "sift1m"))
     do_sweep = args.sweep == "on" or (args.sweep == "auto" and w.name == "sift1m")
+    grid = ([4, 6, 8, 10], [1, 2, 3]) if w.n <= 1_000_000 else ([6, 10, 16], [2, 3])
+    if do_learned:
+        key = "learned_bf16" if datagen.WORKLOADS[LEARNED_FORM[w.name]].precision == "bf16" else "learned"
+        log(f"learned form ({key})")
+        out[key], ids_l = learned_form(torch, K, X, X_t, args, value, w, queries, kth,
+                                       grid if do_sweep and w.name != "sift1m" else None)
+        out[key]["recall@10"] = round(recall_at(X, ids_l, queries, kth, 10), 5)
+        log(f"  {out[key]['points_per_s']:.0f} points/s, recall {out[key]['recall@10']}")
     if do_sweep:
         log("sweep")
-        out["sweep"] = sweep(torch, K, w, X, X_t, queries, kth, [4, 6, 8, 10], [1, 2, 3])
+        out["sweep"] = sweep(torch, K, w, X, X_t, queries, kth, *grid)
     if args.cpu_sample > 0:
         log(f"cpu baseline on {args.cpu_sample} points")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
