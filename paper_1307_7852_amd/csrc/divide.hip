@@ -41,42 +41,41 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total) {
   return base + x - v;
 }
 
-// Walks the histograms of passes 0..npass-1 of segment `sl` and returns the
-// selected key prefix and the remaining rank (block-uniform result).
-__device__ void resolve(const uint32_t* __restrict__ hist, uint32_t sl, uint32_t left, int npass, uint32_t* prefix,
-                        uint32_t* rank, int* sh) {
-  uint32_t pre = 0, r = left;
-  for (int q = 0; q < npass; ++q) {
-    const uint32_t* h = hist + (size_t)sl * HIST_TOTAL + c_hist_base[q];
-    int nb = HB[q];
-    int per = nb / DIV_THREADS;            // 8 or 4 bins per thread
-    int b0 = threadIdx.x * per;
-    int mysum = 0;
-    for (int i = 0; i < per; ++i) mysum += (int)h[b0 + i];
-    int tot;
-    int before = block_excl_scan(mysum, sh, &tot);
-    // the thread whose bins straddle rank r finds the bin
-    if ((uint32_t)before <= r && r < (uint32_t)(before + mysum)) {
-      uint32_t c = before;
-      for (int i = 0; i < per; ++i) {
-        uint32_t hv = h[b0 + i];
-        if (r < c + hv) {
-          sh[8] = b0 + i;
-          sh[9] = (int)c;
-          break;
-        }
-        c += hv;
-      }
-    }
-    __syncthreads();
-    uint32_t bin = (uint32_t)sh[8], below = (uint32_t)sh[9];
-    __syncthreads();
-    int bits = (q == 2) ? 10 : 11;
-    pre = (pre << bits) | bin;
-    r -= below;
+// After histogram pass q of a level: each segment's key prefix after q + 1
+// passes and the rank of the left child's last key inside that prefix, from
+// the previous pass's (prefix, rank) and one scan of pass q's histogram.  One
+// workgroup per segment, once per pass; the pass kernels of every chunk of
+// the segment then read two words instead of walking the histograms.
+__global__ __launch_bounds__(DIV_THREADS) void k_resolve_step(DivideLevelArgs a, int q) {
+  if (a.skip && *a.skip) return;   // uniform: a later division of a stopped build
+  __shared__ int sh[16];
+  const uint32_t sl = blockIdx.x;
+  uint32_t* g = a.hist + (size_t)sl * HIST_TOTAL;
+  uint32_t pre = 0, r = a.segs[sl].left;
+  if (q > 0) {
+    pre = g[HIST_PR + 2 * (q - 1)];
+    r = g[HIST_PR + 2 * (q - 1) + 1];
   }
-  *prefix = pre;
-  *rank = r;
+  const uint32_t* h = g + c_hist_base[q];
+  const int per = HB[q] / DIV_THREADS;   // 8 or 4 bins per thread
+  const int b0 = threadIdx.x * per;
+  int mysum = 0;
+  for (int i = 0; i < per; ++i) mysum += (int)h[b0 + i];
+  int tot;
+  const int before = block_excl_scan(mysum, sh, &tot);
+  if ((uint32_t)before <= r && r < (uint32_t)(before + mysum)) {   // exactly one thread
+    uint32_t c = before;
+    for (int i = 0; i < per; ++i) {
+      const uint32_t hv = h[b0 + i];
+      if (r < c + hv) {
+        const int bits = (q == 2) ? 10 : 11;
+        g[HIST_PR + 2 * q] = (pre << bits) | (uint32_t)(b0 + i);
+        g[HIST_PR + 2 * q + 1] = r - c;
+        break;
+      }
+      c += hv;
+    }
+  }
 }
 
 // --------------------------------------------------------------- direction
@@ -221,11 +220,8 @@ __global__ __launch_bounds__(DIV_THREADS) void k_proj_hist0(DivideLevelArgs a) {
 __global__ __launch_bounds__(DIV_THREADS) void k_hist_pass(DivideLevelArgs a, int pass) {
   if (a.skip && *a.skip) return;   // uniform: a later division of a stopped build
   __shared__ uint32_t lh[HIST_B1];
-  __shared__ int sh[16];
   const ItemDesc it = a.items[blockIdx.x];
-  const SegDesc sd = a.segs[it.seg];
-  uint32_t prefix, rank;
-  resolve(a.hist, it.seg, sd.left, pass, &prefix, &rank, sh);
+  const uint32_t prefix = a.hist[(size_t)it.seg * HIST_TOTAL + HIST_PR + 2 * (pass - 1)];   // from k_resolve_step
   int nb = HB[pass];
   for (int b = threadIdx.x; b < nb; b += DIV_THREADS) lh[b] = 0;
   __syncthreads();
@@ -248,9 +244,7 @@ __global__ __launch_bounds__(DIV_THREADS) void k_part_count(DivideLevelArgs a) {
   if (a.skip && *a.skip) return;   // uniform: a later division of a stopped build
   __shared__ int sh[16];
   const ItemDesc it = a.items[blockIdx.x];
-  const SegDesc sd = a.segs[it.seg];
-  uint32_t pivot, need;
-  resolve(a.hist, it.seg, sd.left, 3, &pivot, &need, sh);
+  const uint32_t pivot = a.hist[(size_t)it.seg * HIST_TOTAL + HIST_PR + 4];   // the left child's last key
   int nl = 0, ne = 0;
   const uint32_t* uks = a.ukeys + (size_t)it.slot * (size_t)a.n + it.start;
   for (uint32_t i = threadIdx.x; i < it.len; i += DIV_THREADS) {
@@ -279,8 +273,8 @@ __global__ __launch_bounds__(DIV_THREADS) void k_part_scatter(DivideLevelArgs a)
     return;
   }
   const SegDesc sd = a.segs[it.seg];
-  uint32_t pivot, need;
-  resolve(a.hist, it.seg, sd.left, 3, &pivot, &need, sh);
+  const uint32_t pivot = a.hist[(size_t)it.seg * HIST_TOTAL + HIST_PR + 4];   // from k_resolve_step
+  const uint32_t need = a.hist[(size_t)it.seg * HIST_TOTAL + HIST_PR + 5];
   // counts of the segment's earlier chunks
   int pl = 0, pe = 0;
   for (uint32_t c = sd.first_item + threadIdx.x; c < blockIdx.x; c += DIV_THREADS) {
@@ -837,9 +831,15 @@ hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s) {
   }
   hipLaunchKernelGGL(k_proj_hist0, dim3(a.n_split), dim3(DIV_THREADS), (size_t)a.d * sizeof(float), s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_resolve_step, dim3(a.n_segs), dim3(DIV_THREADS), 0, s, a, 0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_hist_pass, dim3(a.n_split), dim3(DIV_THREADS), 0, s, a, 1);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_resolve_step, dim3(a.n_segs), dim3(DIV_THREADS), 0, s, a, 1);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_hist_pass, dim3(a.n_split), dim3(DIV_THREADS), 0, s, a, 2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_resolve_step, dim3(a.n_segs), dim3(DIV_THREADS), 0, s, a, 2);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_part_count, dim3(a.n_split), dim3(DIV_THREADS), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;

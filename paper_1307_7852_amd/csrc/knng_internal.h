@@ -79,7 +79,9 @@ struct Plan {
 
 constexpr uint32_t DIV_CHUNK = 2048;      // positions per divide work item
 constexpr uint32_t HIST_B0 = 2048, HIST_B1 = 2048, HIST_B2 = 1024;   // 11 + 11 + 10 key bits
-constexpr uint32_t HIST_TOTAL = HIST_B0 + HIST_B1 + HIST_B2;
+// per segment: the three histograms, then (prefix, rank) after each pass
+constexpr uint32_t HIST_PR = HIST_B0 + HIST_B1 + HIST_B2;
+constexpr uint32_t HIST_TOTAL = HIST_PR + 8;
 
 int64_t leaf_cap(const knng_params& p, int t);
 int plan_tree(const knng_params& p, int t, Plan& out);   // returns knng_status
