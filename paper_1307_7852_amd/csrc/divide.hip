@@ -348,6 +348,7 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
   float4* part = (float4*)(tt + 256);          // G x cw
   __shared__ uint32_t rows[256];
   __shared__ float red[DIV_THREADS / 64];
+  __shared__ float red2[DIV_THREADS / 64];
   __shared__ int redi[DIV_THREADS / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int q = tid % cw, g = tid / cw;
@@ -450,15 +451,7 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
     add(c[0], c[2]);
     return c[0];
   };
-  auto block_sum = [&](float x) -> float {
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    if (lane == 0) red[wv] = x;
-    __syncthreads();
-    float r = 0.f;
-    for (int i = 0; i < DIV_THREADS / 64; ++i) r += red[i];
-    __syncthreads();
-    return r;
-  };
+
   // mean and centring
   slab_sums(nullptr);
   if (tid < cw) {
@@ -479,14 +472,42 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
       *yr = y;
     }
   }
-  centred = true;
-  // normalise the start vector
-  float nn = 0.f;
-  for (int j = tid; j < d; j += DIV_THREADS) nn += v[j] * v[j];
-  nn = block_sum(nn);
+  // The float stage is centred in place; the byte stage stays raw and is
+  // centred algebraically: (y_i - mu).v = y_i.v - mu.v, so t = Y v costs a
+  // conversion and an FMA per byte plus one scalar per row, and w = Y^T t
+  // needs no centring at all because a centred sample's t sums to zero
+  // (sum_i (y_i - mu) = 0 for the sample mean mu).
+  centred = !U8;
+  auto block_sum2 = [&](float& x, float& y) {
+    for (int o = 32; o > 0; o >>= 1) {
+      x += __shfl_xor(x, o);
+      y += __shfl_xor(y, o);
+    }
+    if (lane == 0) {
+      red[wv] = x;
+      red2[wv] = y;
+    }
+    __syncthreads();
+    x = 0.f;
+    y = 0.f;
+    for (int i = 0; i < DIV_THREADS / 64; ++i) {
+      x += red[i];
+      y += red2[i];
+    }
+    __syncthreads();
+  };
+  // normalise the start vector (and, for bytes, mu.v of the unit vector)
+  float nn = 0.f, mv = 0.f;
+  for (int j = tid; j < d; j += DIV_THREADS) {
+    nn += v[j] * v[j];
+    if constexpr (U8) mv = __builtin_fmaf(mu[j], v[j], mv);
+  }
+  block_sum2(nn, mv);
+  float cmv;   // mu . v of the current unit v (bytes only)
   {
     const float inv = nn > 0.f ? 1.0f / sqrtf(nn) : 0.f;
     for (int j = tid; j < d; j += DIV_THREADS) v[j] *= inv;
+    cmv = mv * inv;
   }
   __syncthreads();
   for (int itr = 0; itr < a.pca_iters; ++itr) {
@@ -501,20 +522,26 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
         acc.z = __builtin_fmaf(y.z, vv.z, acc.z);
         acc.w = __builtin_fmaf(y.w, vv.w, acc.w);
       }
-      tt[tid] = (acc.x + acc.y) + (acc.z + acc.w);
+      const float dot = (acc.x + acc.y) + (acc.z + acc.w);
+      tt[tid] = U8 ? dot - cmv : dot;
     }
     __syncthreads();
     slab_sums(tt);   // w = Y^T t, by slabs
-    float sq = 0.f;
+    float sq = 0.f, mw = 0.f;
     float4 w4 = make_float4(0.f, 0.f, 0.f, 0.f);
     if (tid < cw) {
       w4 = col_total(tid);
       sq = w4.x * w4.x + w4.y * w4.y + w4.z * w4.z + w4.w * w4.w;
+      if constexpr (U8) {
+        const float4 m4 = *(const float4*)(mu + 4 * tid);
+        mw = m4.x * w4.x + m4.y * w4.y + m4.z * w4.z + m4.w * w4.w;
+      }
     }
-    sq = block_sum(sq);
-    if (sq > 0.f && tid < cw) {
+    block_sum2(sq, mw);
+    if (sq > 0.f) {
       const float iv = 1.0f / sqrtf(sq);
-      *(float4*)(v + 4 * tid) = make_float4(w4.x * iv, w4.y * iv, w4.z * iv, w4.w * iv);
+      if (tid < cw) *(float4*)(v + 4 * tid) = make_float4(w4.x * iv, w4.y * iv, w4.z * iv, w4.w * iv);
+      cmv = mw * iv;
     }
     __syncthreads();
   }
