@@ -133,6 +133,14 @@ __device__ __forceinline__ void dist2_g16_x8(const float* __restrict__ xa, const
 
 __device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+// Two floats rounded to BF16 (to nearest even) in one 32-bit word, a low.
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  const f32x2 f = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
+}
+
 // Tile element types: FP32 rows padded by 4 floats, BF16 rows by 8 halves;
 // either way consecutive rows start 16 bytes apart modulo the bank width.
 template <int KC, bool BF16>
@@ -403,22 +411,20 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
       if constexpr (!BF16) {
         if (e < TILE_F4) *(float4*)&S.tile[buf].v[row * Tile::STRIDE + col] = v;
         sq = __builtin_fmaf(v.x, v.x, __builtin_fmaf(v.y, v.y, __builtin_fmaf(v.z, v.z, v.w * v.w)));
+      } else if (ikey) {
+        // integers of magnitude <= 256, not centred: exact in BF16, and the
+        // load already zeroed the features past d (no norms are formed here)
+        if (e < TILE_F4) *(uint2*)&S.tile[buf].v[row * Tile::STRIDE + col] = make_uint2(pack_bf16(v.x, v.y), pack_bf16(v.z, v.w));
+        sq = 0.f;
       } else {
-        bool in = e < TILE_F4 && kc + col < d;   // padded features stay exactly zero
-        // integer-key leaves are not centred (their mean is zero): no mean reads
-        const float4 m4 = ikey ? make_float4(0.f, 0.f, 0.f, 0.f)
-                               : make_float4(S.mu[kc + col], S.mu[kc + col + 1], S.mu[kc + col + 2], S.mu[kc + col + 3]);
-        float t0 = in ? bf16_round(v.x - m4.x) : 0.f;
-        float t1 = in ? bf16_round(v.y - m4.y) : 0.f;
-        float t2 = in ? bf16_round(v.z - m4.z) : 0.f;
-        float t3 = in ? bf16_round(v.w - m4.w) : 0.f;
-        if (e < TILE_F4) {   // the four halves in one 8-byte store
-          const uint32_t lo = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)t0) |
-                              ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)t1) << 16);
-          const uint32_t hi = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)t2) |
-                              ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)t3) << 16);
-          *(uint2*)&S.tile[buf].v[row * Tile::STRIDE + col] = make_uint2(lo, hi);
-        }
+        const bool in = e < TILE_F4 && kc + col < d;   // padded features stay exactly zero
+        const float4 m4 = make_float4(S.mu[kc + col], S.mu[kc + col + 1], S.mu[kc + col + 2], S.mu[kc + col + 3]);
+        // the four halves in one 8-byte store; the norm is of the rounded values
+        const uint32_t lo = in ? pack_bf16(v.x - m4.x, v.y - m4.y) : 0u;
+        const uint32_t hi = in ? pack_bf16(v.z - m4.z, v.w - m4.w) : 0u;
+        if (e < TILE_F4) *(uint2*)&S.tile[buf].v[row * Tile::STRIDE + col] = make_uint2(lo, hi);
+        const float t0 = __uint_as_float(lo << 16), t1 = __uint_as_float(lo & 0xFFFF0000u);
+        const float t2 = __uint_as_float(hi << 16), t3 = __uint_as_float(hi & 0xFFFF0000u);
         sq = __builtin_fmaf(t0, t0, __builtin_fmaf(t1, t1, __builtin_fmaf(t2, t2, t3 * t3)));
       }
       if (norms) {   // uniform
@@ -519,7 +525,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     float Lk[KP];
 #pragma unroll
     for (int j = 0; j < KP; ++j) Lk[j] = __uint_as_float(KEY_NONE);
-    f32x16 acc0 = {0}, acc1 = {0};
+    f32x16 acc0 = {0};
     if (!staged) {
       for (int s0 = 0; s0 < 2 && s0 < nsteps; ++s0) {
         float4 rg[STAGE_F4];
@@ -609,16 +615,20 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
 #pragma unroll
             for (int i = 0; i < HALF / 8; ++i) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(trow[i], qf.b[i], acc0, 0, 0, 0);
           } else {
-            if (kci == 0) {
+            // two interleaved chains, the second one local to the step and
+            // added in at its end (a chain carried across steps would be
+            // carried, and copied, through the fast form's steps as well);
+            // a tile's first chunk starts both from the zero constant
+            const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            f32x16 acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(trow[1], qf.b[1], zero, 0, 0, 0);
+            if (kci == 0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(trow[0], qf.b[0], zero, 0, 0, 0);
+            else acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(trow[0], qf.b[0], acc0, 0, 0, 0);
 #pragma unroll
-              for (int r = 0; r < 16; ++r) { acc0[r] = 0.f; acc1[r] = 0.f; }
+            for (int i = 2; i < HALF / 8; ++i) {
+              if (i % 2 == 0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(trow[i], qf.b[i], acc0, 0, 0, 0);
+              else acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(trow[i], qf.b[i], acc1, 0, 0, 0);
             }
-#pragma unroll
-            for (int i = 0; i < HALF / 8; ++i) {
-              bf16x8 cv = trow[i];
-              if (i % 2 == 0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cv, qf.b[i], acc0, 0, 0, 0);
-              else acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cv, qf.b[i], acc1, 0, 0, 0);
-            }
+            acc0 += acc1;
           }
         }
         if (kci == nchunk - 1) {
@@ -648,7 +658,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
                 x = __uint_as_float(__builtin_amdgcn_alignbit(__float_as_uint(acc0[r]), (uint32_t)(c0 + cl) << 23, 23u));
               } else {
                 const float nc = (r & 3) == 0 ? n4[r >> 2].x : (r & 3) == 1 ? n4[r >> 2].y : (r & 3) == 2 ? n4[r >> 2].z : n4[r >> 2].w;
-                const float dv = __builtin_fmaf(-2.0f, BF16 ? acc0[r] + acc1[r] : acc0[r], nq + nc);
+                const float dv = __builtin_fmaf(-2.0f, acc0[r], nq + nc);
                 x = EXACT ? make_ikey(dv, pbase + (uint32_t)cl) : make_key(dv, pbase + (uint32_t)cl);
               }
               if constexpr (EDGE) {
