@@ -208,7 +208,7 @@ template <int R1, int R2, int NCH>
 __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
   __shared__ uint32_t cand_s[4][64 * R1];
   __shared__ float cd_s[4][64 * R1];
-  __shared__ uint32_t htab[4][128 * R1];
+  __shared__ __align__(16) uint32_t htab[4][128 * R1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t vis = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * 4 + w;
   if (vis >= a.n) return;
@@ -348,18 +348,50 @@ __global__ __launch_bounds__(256) void k_prop_forward(PropArgs a) {
   }
   wave_sync();
   if (lane == 0) atomicAdd(&a.diag->prop_candidates[blockIdx.x & (DIAG_SLOTS - 1)], (unsigned long long)U);
-  // 3. first k of N(p) and C_p
+  // 3. first k of N(p) and C_p.  N(p) is sorted and C_p holds none of its
+  //    ids, so only the candidates keyed below N(p)'s k-th can enter (W of
+  //    them, few once the graph is good): none leaves N(p) as it is; up to
+  //    8 are inserted one by one; up to 64 - k are sorted with N(p) in one
+  //    register; more, and all k + U keys are sorted.
   const uint64_t nbkey = lane < k ? pack_did(nbd, nb) : ~0ull;
-  uint64_t v[R2];
-#pragma unroll
-  for (int r = 0; r < R2; ++r) {
-    int e = r * 64 + lane;
-    uint64_t key = ~0ull;
-    if (e < k) key = nbkey;                       // e == lane here
-    else if (e - k < U) key = pack_did(cd_s[w][e - k], cand_s[w][e - k]);
-    v[r] = key;
+  const uint64_t kth_p = shfl_u64(nbkey, k - 1);
+  uint64_t* wkeys = reinterpret_cast<uint64_t*>(htab[w]);   // the table's room: free after step 1
+  int W = 0;
+  for (int base = 0; base < U; base += 64) {
+    const int ci = base + lane;
+    const uint64_t key = ci < U ? pack_did(cd_s[w][ci], cand_s[w][ci]) : ~0ull;
+    const bool win = key < kth_p;
+    int cnt;
+    const int slot = W + wave_prefix_count(win, lane, &cnt);
+    if (win && slot < 64 - k) wkeys[slot] = key;
+    W += cnt;
   }
-  wave_bitonic<R2, 64 * R2, uint64_t>(v, lane);
+  uint64_t v[R2];
+  if (k + W <= 64) {
+    wave_sync();
+    if (W <= 8) {
+      v[0] = nbkey;
+      for (int i = 0; i < W; ++i) {   // the largest entry falls off
+        const uint64_t x = wkeys[i];
+        const uint64_t prev = shfl_up_u64(v[0], 1);
+        if (x < v[0]) v[0] = (lane == 0 || x > prev) ? x : prev;
+      }
+    } else {
+      uint64_t v1[1] = {lane < k ? nbkey : lane < k + W ? wkeys[lane - k] : ~0ull};
+      wave_bitonic<1, 64, uint64_t>(v1, lane);
+      v[0] = v1[0];
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      int e = r * 64 + lane;
+      uint64_t key = ~0ull;
+      if (e < k) key = nbkey;                       // e == lane here
+      else if (e - k < U) key = pack_did(cd_s[w][e - k], cand_s[w][e - k]);
+      v[r] = key;
+    }
+    wave_bitonic<R2, 64 * R2, uint64_t>(v, lane);
+  }
   uint32_t* oi = a.pairwise ? a.fwd_ids : a.ids_out;
   float* od = a.pairwise ? a.fwd_dist : a.dist_out;
   if (lane < k) {

@@ -322,6 +322,62 @@ def test_propagate_round_parity(dev, case):
     say(f"  swaps={swaps} U={U.sum()} proposals={diag['prop_proposals']}")
 
 
+def _lists_by_distance(X, cand):
+    """Rows of candidate ids sorted by (squared distance, id); distances of
+    integer-valued rows are exact integers, so float32 holds them exactly."""
+    Xi = X.astype(np.int64)
+    n, k = cand.shape
+    ids = np.empty((n, k), dtype=np.uint32)
+    dist = np.empty((n, k), dtype=np.float32)
+    for i in range(n):
+        c = cand[i].astype(np.int64)
+        dd = ((Xi[c] - Xi[i]) ** 2).sum(axis=1)
+        order = np.lexsort((c, dd))
+        ids[i], dist[i] = c[order], dd[order].astype(np.float32)
+    return ids, dist
+
+
+@pytest.mark.parametrize("init", ["exact", "random", "shuffled_exact"])
+def test_propagate_round_parity_extreme_inputs(dev, init):
+    """One round from lists no candidate can improve (exact k-NN), from random
+    lists nearly every candidate improves, and from exact lists with half
+    their entries replaced at random: the forward list then takes no entry,
+    more than 64 - k entries, or a handful, so each way of forming it runs."""
+    n, d, k = 3_000, 64, 10
+    say("propagate extreme inputs", init)
+    X = _data("sift", n, d, 81)
+    rng = np.random.default_rng(5)
+    Xi = X.astype(np.int64)
+    sq = (Xi ** 2).sum(axis=1)
+    D = sq[:, None] + sq[None, :] - 2 * Xi @ Xi.T
+    np.fill_diagonal(D, np.iinfo(np.int64).max)
+    exact = np.argsort(D, axis=1, kind="stable")[:, :k]
+    if init == "exact":
+        cand = exact
+    else:
+        cand = np.empty((n, k), dtype=np.int64)
+        for i in range(n):
+            keep = exact[i, : k // 2] if init == "shuffled_exact" else exact[i, :0]
+            pool = rng.choice(n - 1, size=3 * k, replace=False)
+            pool = pool + (pool >= i)
+            extra = [int(x) for x in pool if x not in set(keep.tolist())][: k - len(keep)]
+            cand[i] = np.concatenate([keep, np.array(extra, dtype=np.int64)])
+    in_ids, in_d = _lists_by_distance(X, cand)
+    kp, _ = _params(n, d, k, T=1, leaf_max=64, seed=3)
+    X_t = torch.from_numpy(X).to(dev)
+    ids = torch.from_numpy(in_ids.view(np.int32).copy()).to(dev)
+    dist = torch.from_numpy(in_d.copy()).to(dev)
+    ws = K.alloc_workspace(kp, K.OP_PROPAGATE, dev)
+    K.propagate(kp, X_t, ids, dist, 1, ws)
+    torch.cuda.synchronize()
+    gi, gd = ids.cpu().numpy().view(np.uint32), dist.cpu().numpy()
+    oi, od, U = O.propagate_round(X, in_ids, k, True)
+    assert compare_rows(X, gi, gd, oi, range(n)) == 0
+    assert np.array_equal(gi, oi)
+    if init == "exact":
+        assert np.array_equal(gi, in_ids)
+
+
 def test_propagate_multi_round_matches_repeated_single(dev):
     say("propagate 3 rounds")
     n, d, k = 5000, 16, 8
