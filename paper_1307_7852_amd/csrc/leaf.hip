@@ -253,7 +253,8 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
   using C = Cfg<KP, W>;
   using Tile = TileT<KC, BF16>;
   constexpr int LS = C::LS;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, h = lane >> 5, r32 = lane & 31;
+  const int tid = threadIdx.x, lane = tid & 63, h = lane >> 5, r32 = lane & 31;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform (a scalar)
   const int d = a.d, k = a.k;
   const uint32_t L = key;
   if (m <= 0) return;
@@ -274,7 +275,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     S.max_n = 0u;
   }
   // exact integer keys when the whole data set allows them (uniform)
-  const bool ikey = (a.diag->exact_flags & (BF16 ? EXACT_BF16 : EXACT_FP32)) != 0u;
+  const bool ikey = (__builtin_amdgcn_readfirstlane(a.diag->exact_flags) & (BF16 ? EXACT_BF16 : EXACT_FP32)) != 0u;   // uniform
   __syncthreads();
   // ---- BF16: leaf mean, coalesced (threads over features x row groups).
   // A leaf whose values are all integers of magnitude <= 256 is BF16-exact
@@ -639,60 +640,53 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
           const uint32_t pbase = (uint32_t)(c0 + 4 * h);
           const bool diag = (c0 == qbase);   // uniform: the tile holding the wave's own queries
           const bool ragged = c0 + TILE > m;  // uniform: the last tile has padding rows
-          // EXACT: integer keys; EDGE: the tile needs the self-pair or padding
-          // masks; KI: list entries kept (integer keys need only the k smallest:
-          // KP/2, 5KP/8, 3KP/4 or KP, the first that holds k); FAST: keys from
-          // the Gram's bits, their position without the lane half 4h (bit 2,
-          // set before the halves merge)
-          auto insert_tile = [&](auto exact_tag, auto edge_tag, auto len_tag, auto fast_tag) {
+          // The tile's 16 keys per lane, then the masks (uniform branch: only
+          // the tile holding the wave's own queries, or padding rows when the
+          // keys are integers), then one insertion for all key forms.
+          // EXACT: integer keys; FAST: keys from the Gram's bits, their
+          // position without the lane half 4h (bit 2, set before the halves
+          // merge); KI: list entries kept (integer keys need only the k
+          // smallest: KP/2, 5KP/8, 3KP/4 or KP, the first that holds k)
+          float x[16];
+          auto make_keys = [&](auto exact_tag, auto fast_tag) {
             constexpr bool EXACT = decltype(exact_tag)::value;
-            constexpr bool EDGE = decltype(edge_tag)::value;
-            constexpr int KI = decltype(len_tag)::value;
             constexpr bool FAST = decltype(fast_tag)::value;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
               const int cl = 8 * (r >> 2) + (r & 3);
-              float x;
               if constexpr (FAST) {
-                // (bits << 9) | position; padding rows (ragged tile) are masked below
-                x = __uint_as_float(__builtin_amdgcn_alignbit(__float_as_uint(acc0[r]), (uint32_t)(c0 + cl) << 23, 23u));
+                // (bits << 9) | position; padding rows are masked below
+                x[r] = __uint_as_float(__builtin_amdgcn_alignbit(__float_as_uint(acc0[r]), (uint32_t)(c0 + cl) << 23, 23u));
               } else {
                 const float nc = (r & 3) == 0 ? n4[r >> 2].x : (r & 3) == 1 ? n4[r >> 2].y : (r & 3) == 2 ? n4[r >> 2].z : n4[r >> 2].w;
                 const float dv = __builtin_fmaf(-2.0f, acc0[r], nq + nc);
-                x = EXACT ? make_ikey(dv, pbase + (uint32_t)cl) : make_key(dv, pbase + (uint32_t)cl);
+                x[r] = EXACT ? make_ikey(dv, pbase + (uint32_t)cl) : make_key(dv, pbase + (uint32_t)cl);
               }
-              if constexpr (EDGE) {
-                if (diag && (cl + 4 * h == r32)) x = __uint_as_float(KEY_NONE);
-                if (EXACT && ragged && (int)pbase + cl >= m) x = __uint_as_float(KEY_NONE);
-              }
-              list_insert_head<KI>(Lk, x);
             }
+            if (diag || (EXACT && ragged)) {
+#pragma unroll
+              for (int r = 0; r < 16; ++r) {
+                const int cl = 8 * (r >> 2) + (r & 3);
+                if (diag && (cl + 4 * h == r32)) x[r] = __uint_as_float(KEY_NONE);
+                if (EXACT && ragged && (int)pbase + cl >= m) x[r] = __uint_as_float(KEY_NONE);
+              }
+            }
+          };
+          auto insert = [&](auto len_tag) {
+            constexpr int KI = decltype(len_tag)::value;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) list_insert_head<KI>(Lk, x[r]);
           };
           using T_ = std::true_type;
           using F_ = std::false_type;
-          using KFull = std::integral_constant<int, KP>;
-          using KHalf = std::integral_constant<int, KP / 2>;
-          using K58 = std::integral_constant<int, KP / 2 + KP / 8>;
-          using K3q = std::integral_constant<int, KP - KP / 4>;
-          auto tiers = [&](auto fast_tag) {
-            const bool edge = diag || ragged;
-            if (k <= KP / 2) {
-              if (edge) insert_tile(T_{}, T_{}, KHalf{}, fast_tag); else insert_tile(T_{}, F_{}, KHalf{}, fast_tag);
-            } else if (k <= KP / 2 + KP / 8) {
-              if (edge) insert_tile(T_{}, T_{}, K58{}, fast_tag); else insert_tile(T_{}, F_{}, K58{}, fast_tag);
-            } else if (k <= KP - KP / 4) {
-              if (edge) insert_tile(T_{}, T_{}, K3q{}, fast_tag); else insert_tile(T_{}, F_{}, K3q{}, fast_tag);
-            } else {
-              if (edge) insert_tile(T_{}, T_{}, KFull{}, fast_tag); else insert_tile(T_{}, F_{}, KFull{}, fast_tag);
-            }
-          };
-          if (fastkey) {
-            tiers(T_{});
-          } else if (ikey) {
-            tiers(F_{});
-          } else {
-            if (diag) insert_tile(F_{}, T_{}, KFull{}, F_{}); else insert_tile(F_{}, F_{}, KFull{}, F_{});
-          }
+          if (fastkey) make_keys(T_{}, T_{});
+          else if (ikey) make_keys(T_{}, F_{});
+          else make_keys(F_{}, F_{});
+          const int kt = ikey ? k : KP;   // float keys keep the whole list
+          if (kt <= KP / 2) insert(std::integral_constant<int, KP / 2>{});
+          else if (kt <= KP / 2 + KP / 8) insert(std::integral_constant<int, KP / 2 + KP / 8>{});
+          else if (kt <= KP - KP / 4) insert(std::integral_constant<int, KP - KP / 4>{});
+          else insert(std::integral_constant<int, KP>{});
         }
       }
       if constexpr (DEEP) {
@@ -887,7 +881,7 @@ __global__ __launch_bounds__((Cfg<KP, W>::THREADS)) void k_leaf(LeafArgs a) {
     uint32_t idx;
     if (a.work) {
       __syncthreads();
-      idx = next;
+      idx = __builtin_amdgcn_readfirstlane(next);   // every thread read the same value: a scalar
       __syncthreads();
       if (idx >= a.n_work) break;
       if (threadIdx.x == 0) following = atomicAdd(a.counter, 1u);
