@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_exact_check(const float* __restrict__ X
 
 // One leaf: members perm[off .. off+m), rows written to ids/dist (already
 // offset to the leaf's division).  `key` names the leaf in the fallback list.
-template <int KC, int KP, bool BF16, int W>
+template <int KC, int KP, bool BF16, int W, int KT>
 __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, BF16, W>& S, const uint32_t* __restrict__ perm,
                                           uint32_t* __restrict__ ids_out, float* __restrict__ dist_out, int64_t off,
                                           int m, uint32_t key) {
@@ -682,11 +682,16 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
           if (fastkey) make_keys(T_{}, T_{});
           else if (ikey) make_keys(T_{}, F_{});
           else make_keys(F_{}, F_{});
-          const int kt = ikey ? k : KP;   // float keys keep the whole list
-          if (kt <= KP / 2) insert(std::integral_constant<int, KP / 2>{});
-          else if (kt <= KP / 2 + KP / 8) insert(std::integral_constant<int, KP / 2 + KP / 8>{});
-          else if (kt <= KP - KP / 4) insert(std::integral_constant<int, KP - KP / 4>{});
-          else insert(std::integral_constant<int, KP>{});
+          if constexpr (KT > 0) {   // the tier fixed by the instance (KT >= k)
+            if (ikey) insert(std::integral_constant<int, KT>{});
+            else insert(std::integral_constant<int, KP>{});   // float keys keep the whole list
+          } else {
+            const int kt = ikey ? k : KP;
+            if (kt <= KP / 2) insert(std::integral_constant<int, KP / 2>{});
+            else if (kt <= KP / 2 + KP / 8) insert(std::integral_constant<int, KP / 2 + KP / 8>{});
+            else if (kt <= KP - KP / 4) insert(std::integral_constant<int, KP - KP / 4>{});
+            else insert(std::integral_constant<int, KP>{});
+          }
         }
       }
       if constexpr (DEEP) {
@@ -864,7 +869,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
 // Single-division mode: one workgroup per leaf.  Batched mode: a persistent
 // grid; each workgroup takes the next leaf from the work list (largest
 // first) until the list is exhausted, so every workgroup reaches the exit.
-template <int KC, int KP, bool BF16, int W>
+template <int KC, int KP, bool BF16, int W, int KT>
 __global__ __launch_bounds__((Cfg<KP, W>::THREADS)) void k_leaf(LeafArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using Sh = LeafShared<KC, KP, BF16, W>;
@@ -905,7 +910,7 @@ __global__ __launch_bounds__((Cfg<KP, W>::THREADS)) void k_leaf(LeafArgs a) {
       off = a.leaf_off[idx];
       m = (int)(a.leaf_off[idx + 1] - off);
     }
-    leaf_body<KC, KP, BF16, W>(a, S, perm, ids_out, dist_out, off, m, idx);
+    leaf_body<KC, KP, BF16, W, KT>(a, S, perm, ids_out, dist_out, off, m, idx);
     if (m > 0) rows += (unsigned long long)m;
     if (a.work && threadIdx.x == 0) next = following;
     __syncthreads();
@@ -992,14 +997,14 @@ __global__ __launch_bounds__(256) void k_leaf_exact(LeafArgs a) {
   }
 }
 
-template <int KC, int KP, bool BF16, int W>
+template <int KC, int KP, bool BF16, int W, int KT>
 hipError_t launch_leaf_t(const LeafArgs& a, hipStream_t s) {
   using Sh = LeafShared<KC, KP, BF16, W>;
   if constexpr (sizeof(Sh) + 64 > 160 * 1024) {
     return hipErrorInvalidConfiguration;   // this tile shape does not fit a CU's LDS
   } else {
     size_t shm = sizeof(Sh);
-    auto kern = k_leaf<KC, KP, BF16, W>;
+    auto kern = k_leaf<KC, KP, BF16, W, KT>;
     constexpr int THREADS = Cfg<KP, W>::THREADS;
     static int per_cu = 0;
     if (per_cu == 0) {
@@ -1026,8 +1031,19 @@ hipError_t launch_leaf_t(const LeafArgs& a, hipStream_t s) {
 template <int KC, int KP, bool BF16>
 hipError_t launch_leaf_w(const LeafArgs& a, hipStream_t s) {
   const int w = a.waves ? a.waves : (KP <= 32 ? 8 : 4);
-  if (w == 8) return launch_leaf_t<KC, KP, BF16, 8>(a, s);
-  if (w == 4) return launch_leaf_t<KC, KP, BF16, 4>(a, s);
+  if (w == 8) {
+    // the common shape (d in (64, 128], k + rerank_m <= 16, 8 waves) has an
+    // instance per list-length tier, so its steps hold one insertion
+    if constexpr (KC == 128 && KP == 16) {
+      if (a.k <= KP / 2) return launch_leaf_t<KC, KP, BF16, 8, KP / 2>(a, s);
+      if (a.k <= KP / 2 + KP / 8) return launch_leaf_t<KC, KP, BF16, 8, KP / 2 + KP / 8>(a, s);
+      if (a.k <= KP - KP / 4) return launch_leaf_t<KC, KP, BF16, 8, KP - KP / 4>(a, s);
+      return launch_leaf_t<KC, KP, BF16, 8, KP>(a, s);
+    } else {
+      return launch_leaf_t<KC, KP, BF16, 8, 0>(a, s);
+    }
+  }
+  if (w == 4) return launch_leaf_t<KC, KP, BF16, 4, 0>(a, s);
   return hipErrorInvalidValue;
 }
 
