@@ -379,9 +379,10 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
   // Every thread issues all STAGE_F4 loads unconditionally, so the number of
   // loads in flight is fixed and the Gram's MFMAs need not wait for this
   // prefetch: rows past the leaf repeat its last member (the padding norm
-  // keeps them out of every list) and features past d are zeroed by a
-  // multiply, not a select, which the compiler would turn into a branch
-  // around the load.
+  // keeps them out of every list); columns past d read column 0 and are
+  // zeroed when the values are stored (a select there, after the load, not
+  // around it), which a d that is a multiple of KC never needs.
+  const bool dfull = d % KC == 0 && TILE_F4 % C::THREADS == 0;   // uniform
   auto stage_load = [&](int st, float4 (&rg)[STAGE_F4]) {
     const int t = step_tile(st);
     int c0 = t * TILE, kc = (st - t * nchunk) * KC;
@@ -392,9 +393,10 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
       int cp = c0 + row;
       const bool colok = e < TILE_F4 && kc + col < d;
       const int cpc = cp < m ? cp : m - 1;
-      const float keep = colok ? 1.0f : 0.0f;
-      const float4 v = *(const float4*)(a.X + (size_t)S.ids[cpc] * d + (colok ? kc + col : 0));
-      rg[u] = make_float4(v.x * keep, v.y * keep, v.z * keep, v.w * keep);
+      // element offset id * d + column as one 32 x 32 + 64-bit multiply-add
+      const uint64_t eo = (uint64_t)S.ids[cpc] * (uint32_t)d + (uint32_t)(colok ? kc + col : 0);
+      const float4 v = *(const float4*)(a.X + eo);
+      rg[u] = v;
     }
   };
   // registers -> LDS; on the first pass of a centred BF16 leaf also the
@@ -408,6 +410,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
       int e = tid + u * C::THREADS;
       int row = e / F4_PER_ROW, col = (e % F4_PER_ROW) * 4;
       float4 v = rg[u];
+      if (!dfull && !(e < TILE_F4 && kc + col < d)) v = make_float4(0.f, 0.f, 0.f, 0.f);   // padded features
       float sq;
       if constexpr (!BF16) {
         if (e < TILE_F4) *(float4*)&S.tile[buf].v[row * Tile::STRIDE + col] = v;
