@@ -320,10 +320,12 @@ def cpu_baseline(w, n_sample):
     Xs = datagen.make(w, n=n_sample)
     op = O.Params(n=n_sample, d=w.d, k=w.k, T=w.T, leaf_max=w.leaf_max, leaf_cap_cycle=w.leaf_cap_cycle,
                   q_lo_pm=w.q_lo_pm, q_hi_pm=w.q_hi_pm, rounds=w.rounds, pairwise=True, seed=w.seed + 1)
-    t0 = time.perf_counter()
-    O.build(Xs, op, split="pca" if w.split == "pca" else "rp", metric=w.metric, visit_max=w.visit_max,
-            rate_permille=w.rate_permille)
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):   # BLAS on one thread: the figure is single-core
+        t0 = time.perf_counter()
+        O.build(Xs, op, split="pca" if w.split == "pca" else "rp", metric=w.metric, visit_max=w.visit_max,
+                rate_permille=w.rate_permille)
+        dt = time.perf_counter() - t0
     return {"value": round(n_sample / dt, 2), "unit": "points/s", "cores": 1, "kind": "oracle",
             "sample": f"whole method on {n_sample} points of the same generator ({dt:.1f} s); "
                       f"host has {os.cpu_count()} logical cores, the oracle runs on one"}
@@ -338,7 +340,7 @@ def main():
     ap.add_argument("--T", type=int, default=None, help="override the number of divisions")
     ap.add_argument("--rounds", type=int, default=None, help="override the propagation rounds")
     ap.add_argument("--queries", type=int, default=10000, help="recall sample size")
-    ap.add_argument("--cpu-sample", type=int, default=20000, help="points for the CPU oracle leg (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=30000, help="points for the CPU oracle leg (0: skip)")
     ap.add_argument("--train-steps", type=int, default=1500, help="Adam steps for the learned division")
     ap.add_argument("--learned", choices=["auto", "on", "off"], default="auto",
                     help="measure the BF16 + learned form beside sift1m (auto: only for sift1m)")
