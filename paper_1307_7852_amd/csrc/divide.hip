@@ -199,7 +199,9 @@ __global__ __launch_bounds__(DIV_THREADS) void k_proj_hist0(DivideLevelArgs a) {
   __shared__ uint32_t lh[HIST_B0];
   const ItemDesc it = a.items[blockIdx.x];
   const SegDesc sd = a.segs[it.seg];
-  for (int b = threadIdx.x; b < (int)HIST_B0; b += DIV_THREADS) lh[b] = 0;
+  const bool hist = a.small == 0u;   // uniform: small segments are selected in LDS instead
+  if (hist)
+    for (int b = threadIdx.x; b < (int)HIST_B0; b += DIV_THREADS) lh[b] = 0;
   load_direction(a, sd, dir, it.start == sd.off);
   const size_t base = (size_t)it.slot * (size_t)a.n;
   const bool u8 = a.X8 && (*a.flags & EXACT_U8) != 0u;   // uniform
@@ -209,8 +211,9 @@ __global__ __launch_bounds__(DIV_THREADS) void k_proj_hist0(DivideLevelArgs a) {
     float key = u8 ? dot_seq_u8(a.X8 + (size_t)row * a.d, dir, a.d) : dot_seq(a.X + (size_t)row * a.d, dir, a.d);
     uint32_t uk = ordered_key(key);
     a.ukeys[pos] = uk;
-    atomicAdd(&lh[uk >> 21], 1u);
+    if (hist) atomicAdd(&lh[uk >> 21], 1u);
   }
+  if (!hist) return;
   __syncthreads();
   uint32_t* gh = a.hist + (size_t)it.seg * HIST_TOTAL;
   for (int b = threadIdx.x; b < (int)HIST_B0; b += DIV_THREADS)
@@ -238,6 +241,76 @@ __global__ __launch_bounds__(DIV_THREADS) void k_hist_pass(DivideLevelArgs a, in
   uint32_t* gh = a.hist + (size_t)it.seg * HIST_TOTAL + c_hist_base[pass];
   for (int b = threadIdx.x; b < nb; b += DIV_THREADS)
     if (lh[b]) atomicAdd(&gh[b], lh[b]);
+}
+
+// A level whose segments all hold at most DIV_SMALL points: one workgroup
+// per segment loads the segment's keys into LDS, finds the key of rank
+// `left` by four 8-bit radix passes over LDS histograms, and writes the
+// stable partition (keys below it, then the first `need` keys equal to it,
+// left; the rest right, each side in position order) -- the same pivot,
+// count and order as the histogram passes and chunked scatter of larger
+// segments.  The segment's first item does the work; copy items copy.
+__global__ __launch_bounds__(DIV_THREADS) void k_small_partition(DivideLevelArgs a) {
+  if (a.skip && *a.skip) return;   // uniform: a later division of a stopped build
+  __shared__ uint32_t keys[DIV_SMALL];
+  __shared__ uint32_t hb[256];
+  __shared__ uint32_t pick[2];
+  __shared__ int sh[16];
+  const ItemDesc it = a.items[blockIdx.x];
+  const size_t base = (size_t)it.slot * (size_t)a.n;
+  const uint32_t* pin = a.perm_in + base;
+  uint32_t* pout = a.perm_out + base;
+  if (it.seg == 0xFFFFFFFFu) {   // positions outside this level's internal nodes
+    for (uint32_t i = threadIdx.x; i < it.len; i += DIV_THREADS) pout[it.start + i] = pin[it.start + i];
+    return;
+  }
+  const SegDesc sd = a.segs[it.seg];
+  if (it.start != sd.off) return;   // uniform: not the segment's first item
+  const uint32_t m = sd.m;
+  for (uint32_t i = threadIdx.x; i < m; i += DIV_THREADS) keys[i] = a.ukeys[base + sd.off + i];
+  uint32_t prefix = 0, r = sd.left;   // rank of the pivot among the segment's keys
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 24 - 8 * pass;
+    hb[threadIdx.x] = 0;   // 256 threads, 256 bins
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < m; i += DIV_THREADS) {
+      const uint32_t uk = keys[i];
+      if (pass == 0 || (uk >> (shift + 8)) == prefix) atomicAdd(&hb[(uk >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    const int c = (int)hb[threadIdx.x];
+    int tot;
+    const int before = block_excl_scan(c, sh, &tot);
+    if ((uint32_t)before <= r && r < (uint32_t)(before + c)) {   // exactly one thread
+      pick[0] = threadIdx.x;
+      pick[1] = (uint32_t)before;
+    }
+    __syncthreads();
+    prefix = (prefix << 8) | pick[0];
+    r -= pick[1];
+    __syncthreads();   // pick and hb are rewritten by the next pass
+  }
+  const uint32_t pivot = prefix, need = r;   // need: keys equal to the pivot that go left
+  int less_before = 0, eq_before = 0;
+  for (uint32_t t0 = 0; t0 < m; t0 += DIV_THREADS) {
+    const uint32_t i = t0 + threadIdx.x;
+    const bool valid = i < m;
+    const uint32_t uk = valid ? keys[i] : 0xFFFFFFFFu;
+    const int isl = valid && uk < pivot, ise = valid && uk == pivot;
+    int tl, te;
+    const int rl = block_excl_scan(isl, sh, &tl);
+    const int re = block_excl_scan(ise, sh, &te);
+    if (valid) {
+      const uint32_t nless = (uint32_t)(less_before + rl), neq = (uint32_t)(eq_before + re);
+      uint32_t dest;
+      if (isl) dest = sd.off + nless + (neq < need ? neq : need);
+      else if (ise && neq < need) dest = sd.off + nless + neq;
+      else dest = sd.off + sd.left + (i - nless - (neq < need ? neq : need));
+      pout[dest] = pin[sd.off + i];
+    }
+    less_before += tl;
+    eq_before += te;
+  }
 }
 
 __global__ __launch_bounds__(DIV_THREADS) void k_part_count(DivideLevelArgs a) {
@@ -823,7 +896,7 @@ hipError_t launch_iota(uint32_t* p, uint32_t n, uint32_t slots, hipStream_t s) {
 
 hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s) {
   hipError_t e;
-  if ((e = launch_fill_u32(a.hist, 0u, (size_t)a.n_segs * HIST_TOTAL, s)) != hipSuccess) return e;
+  if (!a.small && (e = launch_fill_u32(a.hist, 0u, (size_t)a.n_segs * HIST_TOTAL, s)) != hipSuccess) return e;
   if (a.pca_iters > 0 && !a.dirs) {
     size_t base = (size_t)(2 * a.d + 256) * sizeof(float);
     if (a.d <= PCA_COV_DMAX) {
@@ -858,6 +931,10 @@ hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s) {
   }
   hipLaunchKernelGGL(k_proj_hist0, dim3(a.n_split), dim3(DIV_THREADS), (size_t)a.d * sizeof(float), s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (a.small) {
+    hipLaunchKernelGGL(k_small_partition, dim3(a.n_items), dim3(DIV_THREADS), 0, s, a);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_resolve_step, dim3(a.n_segs), dim3(DIV_THREADS), 0, s, a, 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_hist_pass, dim3(a.n_split), dim3(DIV_THREADS), 0, s, a, 1);

@@ -454,6 +454,7 @@ int divide_core(const knng_params& p, const Batch& B, const char* blob_dev, cons
     a.X8 = x8;
     a.flags = flags;
     a.skip = skip;
+    a.small = lv.max_seg <= DIV_SMALL ? 1u : 0u;
     HIP_TRY(launch_divide_level(a, s));
   }
   return KNNG_OK;

@@ -78,6 +78,7 @@ struct Plan {
 };
 
 constexpr uint32_t DIV_CHUNK = 2048;      // positions per divide work item
+constexpr uint32_t DIV_SMALL = 2048;      // segments up to this size are selected and split by one workgroup in LDS
 constexpr uint32_t HIST_B0 = 2048, HIST_B1 = 2048, HIST_B2 = 1024;   // 11 + 11 + 10 key bits
 // per segment: the three histograms, then (prefix, rank) after each pass
 constexpr uint32_t HIST_PR = HIST_B0 + HIST_B1 + HIST_B2;
@@ -141,6 +142,7 @@ struct DivideLevelArgs {
   const uint8_t* X8;         // nullable: one-byte copy of X, read instead of X when *flags has EXACT_U8
   const uint32_t* flags;
   const uint32_t* skip;      // nullable: when *skip != 0 every kernel of the level returns at once
+  uint32_t small;            // every segment of the level has at most DIV_SMALL points
 };
 hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s);
 // compute units of the current device (cached after the first call)
