@@ -419,7 +419,9 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_lds(DivideLevelArgs a) {
   float* mu = v + d;                           // d
   float* tt = mu + d;                          // 256
   float4* part = (float4*)(tt + 256);          // G x cw
-  __shared__ uint32_t rows[256];
+  // the sample's row ids share the partials' room: read only while staging,
+  // before the first partial is written (each segment starts after a barrier)
+  uint32_t* rows = reinterpret_cast<uint32_t*>(part);
   __shared__ float red[DIV_THREADS / 64];
   __shared__ float red2[DIV_THREADS / 64];
   __shared__ int redi[DIV_THREADS / 64];
@@ -914,11 +916,11 @@ hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s) {
         attr = true;
       }
       // as many workgroups as the CUs' LDS holds at once (160 KB each, with
-      // the kernel's 1056 static bytes), at most eight per CU; they stride
+      // the kernel's 48 static bytes), at most eight per CU; they stride
       // over the segments
       const unsigned cus = (unsigned)cu_count();
       auto grid = [&](size_t bytes) {
-        const size_t per_cu = std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / (bytes + 1056)));
+        const size_t per_cu = std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / (bytes + 48)));
         return dim3((unsigned)std::min<size_t>(a.n_segs, per_cu * cus));
       };
       hipLaunchKernelGGL(k_pca_lds<false>, grid(shm), dim3(DIV_THREADS), shm, s, a);
