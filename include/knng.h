@@ -147,6 +147,17 @@ const char* knng_status_str(int status);
 /* Description of the calling thread's last failure (static thread-local). */
 const char* knng_last_error(void);
 
+/* Host-side fault injection, for callers that test their own handling of a
+ * failed launch (re-issuing a stage: every entry point is a pure function
+ * of its inputs, parameters and seed).  mode 1 arms a one-shot fault: the
+ * next kernel launch of any entry point, in any thread, returns KNNG_EHIP
+ * without enqueueing that launch or anything after it (work the same call
+ * enqueued before it stays enqueued; outputs are unspecified); mode 0
+ * disarms.  Setting KNNG_FAULT=launch in the environment arms it once when
+ * the library is loaded.  Nothing reaches the GPU.  Returns the previous
+ * state (0 or 1), or KNNG_EINVAL for another mode.  Host only. */
+int knng_inject_fault(int32_t mode);
+
 /* Bytes of workspace entry point `op` needs for parameters `p`
  * (0 on invalid parameters; knng_last_error() then says why).  Host only. */
 size_t knng_workspace_bytes(const knng_params* p, int op);

@@ -4,11 +4,11 @@ ABI of include/knng.h.  This package is the thin Python side: the ctypes
 binding plus torch helpers for device buffers."""
 from . import _lib
 from ._lib import (BF16, FP32, MLP_EMB, MLP_HIDDEN, NONE, OP_BUILD, OP_COLEAF, OP_DIVIDE, OP_LEAF, OP_MERGE,
-                   OP_PROPAGATE, NOALLOC_MAX_N, SPLIT_PCA, SPLIT_RP, METRIC_L2, METRIC_COSINE, normalize, BuildGraph, KnngError, Params, build, build_split, build_timed, coleaf_rate,
+                   OP_PROPAGATE, NOALLOC_MAX_N, SPLIT_PCA, inject_fault, SPLIT_RP, METRIC_L2, METRIC_COSINE, normalize, BuildGraph, KnngError, Params, build, build_split, build_timed, coleaf_rate,
                    divide, leaf_knn, leaf_knn_noalloc, leaf_set_config, leaf_tune, learned_choice, merge, mlp_adam, mlp_forward, mlp_grad, mlp_init, mlp_param_count,
                    mlp_sample_pairs, mlp_train, mlp_workspace_bytes, propagate, read_diag, tree_shape, workspace_bytes)
 
-__all__ = ["Params", "KnngError", "build", "build_split", "build_timed", "coleaf_rate", "learned_choice", "divide", "leaf_knn", "leaf_knn_noalloc", "merge", "normalize", "METRIC_L2", "METRIC_COSINE",
+__all__ = ["Params", "KnngError", "inject_fault", "build", "build_split", "build_timed", "coleaf_rate", "learned_choice", "divide", "leaf_knn", "leaf_knn_noalloc", "merge", "normalize", "METRIC_L2", "METRIC_COSINE",
            "propagate", "read_diag", "tree_shape", "workspace_bytes", "alloc_workspace", "knn_graph", "NONE", "FP32",
            "BF16", "SPLIT_RP", "SPLIT_PCA", "OP_DIVIDE", "OP_LEAF", "OP_MERGE", "OP_PROPAGATE", "OP_BUILD", "OP_COLEAF",
            "MLP_HIDDEN", "MLP_EMB", "mlp_param_count", "mlp_init", "mlp_forward", "mlp_workspace_bytes", "mlp_grad",

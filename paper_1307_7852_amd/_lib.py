@@ -93,6 +93,7 @@ def _load():
     sig = {
         "knng_status_str": (ctypes.c_char_p, [i32]),
         "knng_last_error": (ctypes.c_char_p, []),
+        "knng_inject_fault": (i32, [ctypes.c_int32]),
         "knng_workspace_bytes": (sz, [P, i32]),
         "knng_normalize": (i32, [i64, i32, vp, vp, vp]),
         "knng_tree_shape": (i32, [P, i32, ctypes.POINTER(i64), i64, ctypes.POINTER(i64), ctypes.POINTER(i64),
@@ -133,7 +134,7 @@ def _load():
 
 
 _lib = _load()
-EXPORTS = ["knng_status_str", "knng_last_error", "knng_workspace_bytes", "knng_tree_shape", "knng_normalize", "knng_divide",
+EXPORTS = ["knng_status_str", "knng_last_error", "knng_inject_fault", "knng_workspace_bytes", "knng_tree_shape", "knng_normalize", "knng_divide",
            "knng_leaf_knn", "knng_leaf_knn_noalloc", "knng_merge", "knng_propagate", "knng_build", "knng_read_diag", "knng_build_timed",
            "knng_build_split", "knng_coleaf_rate", "knng_learned_choice", "knng_mlp_param_count", "knng_mlp_init", "knng_mlp_forward",
            "knng_mlp_workspace_bytes", "knng_mlp_grad", "knng_mlp_adam", "knng_mlp_sample_pairs", "knng_mlp_train",
@@ -167,6 +168,16 @@ def workspace_bytes(p: Params, op: int) -> int:
     if n == 0 and op != OP_MERGE:
         raise KnngError(EINVAL, _lib.knng_last_error().decode())
     return n
+
+
+def inject_fault(mode: int) -> int:
+    """Arm (1) or disarm (0) the library's one-shot launch fault: the next
+    kernel launch of any entry point fails with KNNG_EHIP before it is
+    enqueued.  Returns the previous state.  Host only."""
+    r = _lib.knng_inject_fault(mode)
+    if r < 0:
+        raise KnngError(r, _lib.knng_last_error().decode())
+    return r
 
 
 def tree_shape(p: Params, t: int):

@@ -3,9 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -34,6 +36,25 @@ int fail(int code, const char* fmt, ...) {
   do {                                                                                       \
     hipError_t e_ = (expr);                                                                  \
     if (e_ != hipSuccess) return fail(KNNG_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// Host-side fault injection: when armed (knng_inject_fault, or KNNG_FAULT=launch
+// in the environment when the library is loaded) the next kernel-launch wrapper
+// returns KNNG_EHIP before it enqueues anything, once.  Nothing reaches the GPU.
+std::atomic<int> g_fault_launch{0};
+
+struct FaultFromEnv {
+  FaultFromEnv() {
+    const char* v = std::getenv("KNNG_FAULT");
+    if (v && std::strcmp(v, "launch") == 0) g_fault_launch.store(1);
+  }
+} g_fault_from_env;
+
+#define LAUNCH_TRY(expr)                                                                     \
+  do {                                                                                       \
+    if (g_fault_launch.load(std::memory_order_relaxed) && g_fault_launch.exchange(0))        \
+      return fail(KNNG_EHIP, "%s not launched: injected launch fault", #expr);               \
+    HIP_TRY(expr);                                                                           \
   } while (0)
 
 int validate(const knng_params* p) {
@@ -436,7 +457,7 @@ int divide_core(const knng_params& p, const Batch& B, const char* blob_dev, cons
   const SegDesc* segs = (const SegDesc*)blob_dev;
   const ItemDesc* items = (const ItemDesc*)(blob_dev + B.off_items);
   uint32_t* buf[2] = {buf0, buf1};
-  HIP_TRY(launch_iota(buf[0], (uint32_t)p.n, (uint32_t)B.slots, s));
+  LAUNCH_TRY(launch_iota(buf[0], (uint32_t)p.n, (uint32_t)B.slots, s));
   for (int l = 0; l < B.depth; ++l) {
     const LevelPlan& lv = B.levels[l];
     DivideLevelArgs a{};
@@ -455,7 +476,7 @@ int divide_core(const knng_params& p, const Batch& B, const char* blob_dev, cons
     a.flags = flags;
     a.skip = skip;
     a.small = lv.max_seg <= DIV_SMALL ? 1u : 0u;
-    HIP_TRY(launch_divide_level(a, s));
+    LAUNCH_TRY(launch_divide_level(a, s));
   }
   return KNNG_OK;
 }
@@ -532,7 +553,7 @@ int leaf_single(const knng_params& p, const float* X, const uint32_t* perm, cons
   a.pnorm = (float*)(scratch + L.pnorm);
   a.diag = diag;
   apply_tune(p, 2 * (int64_t)p.leaf_max, a);
-  HIP_TRY(launch_leaf(a, s));
+  LAUNCH_TRY(launch_leaf(a, s));
   return KNNG_OK;
 }
 
@@ -565,6 +586,8 @@ int leaf_batched(const knng_params& p, const Batch& B, const char* blob_dev, con
   }
   a.prepare_only = prepare_only;
   a.skip = skip;
+  if (g_fault_launch.load(std::memory_order_relaxed) && g_fault_launch.exchange(0))
+    return fail(KNNG_EHIP, "launch_leaf not launched: injected launch fault");
   hipError_t e = launch_leaf(a, s);
   if (e == hipErrorInvalidConfiguration || e == hipErrorInvalidValue)
     return fail(KNNG_EUNSUPPORTED, "leaf tile configuration (waves %d, kc %d) does not fit", a.waves, a.kc);
@@ -601,7 +624,7 @@ int prop_core(const knng_params& p, const float* X, uint32_t* ids, float* dist, 
     a.X8 = x8;
     a.visit_max = p.visit_max;
     a.slot_cap = prop_slot_cap(p);
-    HIP_TRY(launch_propagate_round(a, s));
+    LAUNCH_TRY(launch_propagate_round(a, s));
     if (after_round && !(r == rounds - 1 && rounds % 2 == 1)) HIP_TRY(after_round(r));
   }
   if (rounds % 2 == 1) {
@@ -738,6 +761,11 @@ const char* knng_status_str(int status) {
 
 const char* knng_last_error(void) { return g_err; }
 
+int knng_inject_fault(int32_t mode) {
+  if (mode != 0 && mode != 1) return fail(KNNG_EINVAL, "fault mode %d must be 0 or 1", mode);
+  return g_fault_launch.exchange(mode);
+}
+
 size_t knng_workspace_bytes(const knng_params* p, int op) {
   if (validate(p) != KNNG_OK) return 0;
   switch (op) {
@@ -808,7 +836,7 @@ int knng_divide(const knng_params* p, int t, const float* X, const float* dir_ov
   char* w = (char*)ws;
   st = upload_blob(*B, w + L.blob, s);
   if (st) return st;
-  HIP_TRY(zero_diag(w + L.diag, s));
+  LAUNCH_TRY(zero_diag(w + L.diag, s));
   uint32_t* tmp = (uint32_t*)(w + L.tmp);
   uint32_t* b0 = (B->depth % 2 == 0) ? perm : tmp;   // the final permutation lands in `perm`
   uint32_t* b1 = (B->depth % 2 == 0) ? tmp : perm;
@@ -829,7 +857,7 @@ int knng_leaf_knn(const knng_params* p, const float* X, const uint32_t* perm, co
   LeafLayout L = leaf_layout(*p, 1);
   if (ws_bytes < L.total) return fail(KNNG_ENOMEM, "leaf_knn needs %zu workspace bytes, got %zu", L.total, ws_bytes);
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(zero_diag((char*)ws + L.diag, s));
+  LAUNCH_TRY(zero_diag((char*)ws + L.diag, s));
   return leaf_single(*p, X, perm, leaf_off, n_leaves, ids, dist, (char*)ws, (DiagDev*)((char*)ws + L.diag), s);
 }
 
@@ -840,7 +868,7 @@ int knng_merge(const knng_params* p, int n_lists, const uint32_t* ids_in, const 
   if (n_lists < 1 || n_lists > 1024) return fail(KNNG_EINVAL, "n_lists=%d out of [1, 1024]", n_lists);
   if (!ids_in || !dist_in || !ids_out || !dist_out) return fail(KNNG_EINVAL, "null array argument");
   if ((int64_t)n_lists * p->k > 1024) return fail(KNNG_EUNSUPPORTED, "n_lists * k = %d exceeds 1024", n_lists * p->k);
-  HIP_TRY(launch_merge(p->n, p->k, n_lists, ids_in, dist_in, ids_out, dist_out, (hipStream_t)stream,
+  LAUNCH_TRY(launch_merge(p->n, p->k, n_lists, ids_in, dist_in, ids_out, dist_out, (hipStream_t)stream,
                        (int64_t)p->n * p->k, p->k));
   return KNNG_OK;
 }
@@ -855,7 +883,7 @@ int knng_propagate(const knng_params* p, const float* X, uint32_t* ids, float* d
   PropLayout L = prop_layout(*p);
   if (ws_bytes < L.total) return fail(KNNG_ENOMEM, "propagate needs %zu workspace bytes, got %zu", L.total, ws_bytes);
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(zero_diag((char*)ws + L.diag, s));
+  LAUNCH_TRY(zero_diag((char*)ws + L.diag, s));
   return prop_core(*p, X, ids, dist, rounds, (char*)ws, (DiagDev*)((char*)ws + L.diag), nullptr, s);
 }
 
@@ -900,7 +928,7 @@ static int build_impl(const knng_params* p, const float* X, const float* S, int 
     }
   }
   DiagDev* diag = (DiagDev*)(w + BL.diag);
-  HIP_TRY(zero_diag(diag, s));
+  LAUNCH_TRY(zero_diag(diag, s));
   auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord((*ev)[i], s) : hipSuccess; };
   float* pnorm = (float*)(w + BL.pnorm);
   uint8_t* x8 = (uint8_t*)(w + BL.x8);
@@ -915,14 +943,14 @@ static int build_impl(const knng_params* p, const float* X, const float* S, int 
   const float* Sm = S;
   if (p->metric == KNNG_METRIC_COSINE) {
     float* xn = (float*)(w + BL.xn);
-    HIP_TRY(launch_normalize(X, p->n, p->d, xn, s));
+    LAUNCH_TRY(launch_normalize(X, p->n, p->d, xn, s));
     if (S == X) Sm = xn;
     Xm = xn;
   }
   const bool same = Sm == Xm && ds == p->d;
   // one check of X serves every stage: exactness flags, row norms and the
   // one-byte copy that the divide and propagation read when it holds X
-  HIP_TRY(launch_data_check(Xm, p->n, p->d, &diag->exact_flags, pnorm, x8, s));
+  LAUNCH_TRY(launch_data_check(Xm, p->n, p->d, &diag->exact_flags, pnorm, x8, s));
   const uint32_t* order = nullptr;   // division 0's leaf order: the propagation's visiting order
   const uint32_t* n_used = nullptr;
   if (!adaptive) {
@@ -951,13 +979,13 @@ static int build_impl(const knng_params* p, const float* X, const float* S, int 
       st = leaf_batched(*p, *Bt[t], w + BL.blob_t[t], Xm, perm_t, lists_ids + (size_t)t * p->k,
                         lists_dist + (size_t)t * p->k, sh, diag, s, -1, -1, false, pnorm, &diag->stop);
       if (st) return st;
-      HIP_TRY(launch_effective_rate(p->n, p->k, t, lists_ids, p->k, (int64_t)p->T * p->k, p->rate_permille, diag, s));
+      LAUNCH_TRY(launch_effective_rate(p->n, p->k, t, lists_ids, p->k, (int64_t)p->T * p->k, p->rate_permille, diag, s));
     }
     n_used = &diag->div_used;
     HIP_TRY(mark(1));
     HIP_TRY(mark(2));
   }
-  HIP_TRY(launch_merge(p->n, p->k, p->T, lists_ids, lists_dist, ids, dist, s, p->k, (int64_t)p->T * p->k, n_used));
+  LAUNCH_TRY(launch_merge(p->n, p->k, p->T, lists_ids, lists_dist, ids, dist, s, p->k, (int64_t)p->T * p->k, n_used));
   HIP_TRY(mark(3));
   if (p->rounds > 0) {
     st = prop_core(*p, Xm, ids, dist, p->rounds, sh, diag, order, s, [&](int r) { return mark(4 + r); }, x8);
@@ -1033,7 +1061,7 @@ int knng_coleaf_rate(const knng_params* p, int t, const float* S, int32_t ds, co
   st = knng_tree_shape(p, t, nullptr, 0, &n_leaves, &n_int, &depth);
   if (st) return st;
   unsigned long long* count = (unsigned long long*)(w + L.count);
-  HIP_TRY(launch_coleaf(perm, leaf_off, n_leaves, (uint32_t*)(w + L.label), pairs, n_pairs, count, s));
+  LAUNCH_TRY(launch_coleaf(perm, leaf_off, n_leaves, (uint32_t*)(w + L.label), pairs, n_pairs, count, s));
   unsigned long long hc = 0;
   HIP_TRY(hipMemcpyAsync(&hc, count, 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1094,7 +1122,7 @@ int knng_leaf_tune(const knng_params* p, const float* X, void* ws, size_t ws_byt
   uint32_t* permA = (uint32_t*)(w + BL.permA);
   uint32_t* permB = (uint32_t*)(w + BL.permB);
   char* sh = w + BL.shared;
-  HIP_TRY(zero_diag(diag, s));
+  LAUNCH_TRY(zero_diag(diag, s));
   st = divide_core(*p, *B, w + BL.blob, X, nullptr, nullptr, permA, permB, sh, s);
   if (st) return st;
   const uint32_t* perms = (B->depth % 2 == 0) ? permA : permB;
@@ -1196,7 +1224,7 @@ int knng_leaf_knn_noalloc(const knng_params* p, const float* X, const uint32_t* 
   if (st) return st;
   char* w = (char*)sp;
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(zero_diag(w + L.diag, s));
+  LAUNCH_TRY(zero_diag(w + L.diag, s));
   return leaf_single(*p, X, perm, leaf_off, n_leaves, ids, dist, w, (DiagDev*)(w + L.diag), s);
 }
 
@@ -1285,7 +1313,7 @@ int knng_normalize(int64_t n, int32_t d, const float* X, float* Xn, void* stream
   if (n == 0) return KNNG_OK;
   if (!X || !Xn) return fail(KNNG_EINVAL, "null array argument");
   if (!aligned16(X) || !aligned16(Xn)) return fail(KNNG_EINVAL, "X and Xn must be 16-byte aligned");
-  HIP_TRY(launch_normalize(X, n, d, Xn, (hipStream_t)stream));
+  LAUNCH_TRY(launch_normalize(X, n, d, Xn, (hipStream_t)stream));
   return KNNG_OK;
 }
 
@@ -1306,7 +1334,7 @@ int knng_mlp_init(int32_t d, uint64_t seed, float* params, void* stream) {
   if (!params || !aligned16(params)) return fail(KNNG_EINVAL, "params must be non-null and 16-byte aligned");
   const float lim1 = (float)std::sqrt(6.0 / d);
   const float lim2 = (float)std::sqrt(6.0 / (KNNG_MLP_HIDDEN + KNNG_MLP_EMB));
-  HIP_TRY(launch_mlp_init(params, d, seed, lim1, lim2, (hipStream_t)stream));
+  LAUNCH_TRY(launch_mlp_init(params, d, seed, lim1, lim2, (hipStream_t)stream));
   return KNNG_OK;
 }
 
@@ -1322,7 +1350,7 @@ int knng_mlp_forward(int32_t d, int32_t precision, float scale, const float* par
   MlpArgs a{};
   a.params = params; a.X = X; a.d = d; a.scale = scale; a.bf16 = precision == KNNG_BF16;
   a.rows = nullptr; a.R = n; a.Z = Z;
-  HIP_TRY(launch_mlp_forward(a, false, (hipStream_t)stream));
+  LAUNCH_TRY(launch_mlp_forward(a, false, (hipStream_t)stream));
   return KNNG_OK;
 }
 
@@ -1361,8 +1389,8 @@ int mlp_grad_core(int32_t d, int32_t precision, float scale, const float* params
   a.loss_part = (float*)(w + L.lpart); a.n_loss_parts = L.nlp; a.loss = loss;
   a.part = (float*)(w + L.part); a.n_chunks = (int)L.chunks; a.chunk_rows = MLP_CHUNK_ROWS; a.n_params = L.P;
   a.grads = grads;
-  HIP_TRY(launch_mlp_forward(a, true, s));
-  HIP_TRY(launch_mlp_backward(a, s));
+  LAUNCH_TRY(launch_mlp_forward(a, true, s));
+  LAUNCH_TRY(launch_mlp_backward(a, s));
   return KNNG_OK;
 }
 
@@ -1403,7 +1431,7 @@ int knng_mlp_adam(int64_t n, float* params, const float* grads, float* m, float*
     return fail(KNNG_EINVAL, "need 0 <= beta1, beta2 < 1 and eps > 0");
   const float bc1 = (float)(1.0 - std::pow((double)beta1, step));
   const float bc2 = (float)(1.0 - std::pow((double)beta2, step));
-  HIP_TRY(launch_mlp_adam(params, grads, m, v, n, lr, beta1, beta2, eps, bc1, bc2, (hipStream_t)stream));
+  LAUNCH_TRY(launch_mlp_adam(params, grads, m, v, n, lr, beta1, beta2, eps, bc1, bc2, (hipStream_t)stream));
   return KNNG_OK;
 }
 
@@ -1415,7 +1443,7 @@ int knng_mlp_sample_pairs(int64_t n, int32_t k, const uint32_t* ids, uint64_t se
   if (st) return st;
   if (step >= (1u << 28)) return fail(KNNG_EINVAL, "step=%u >= 2^28", step);
   if (!rows || (n_pos > 0 && !ids)) return fail(KNNG_EINVAL, "null array argument");
-  HIP_TRY(launch_mlp_sample(ids, n, k, seed, step, n_pos, n_neg, rows, (hipStream_t)stream));
+  LAUNCH_TRY(launch_mlp_sample(ids, n, k, seed, step, n_pos, n_neg, rows, (hipStream_t)stream));
   return KNNG_OK;
 }
 
@@ -1440,7 +1468,7 @@ int knng_mlp_train(int32_t d, int32_t precision, float scale, float* params, flo
   float* grads = (float*)(w + L.grads);
   for (int32_t i = 0; i < steps; ++i) {
     const int32_t step = step0 + i + 1;
-    HIP_TRY(launch_mlp_sample(graph_ids, n, k, seed, (uint32_t)step, n_pos, n_neg, rows, s));
+    LAUNCH_TRY(launch_mlp_sample(graph_ids, n, k, seed, (uint32_t)step, n_pos, n_neg, rows, s));
     st = mlp_grad_core(d, precision, scale, params, X, rows, n_pos, n_neg, lam, margin, grads,
                        losses ? losses + i : (float*)(w + L.loss), w, L, s);
     if (st) return st;
