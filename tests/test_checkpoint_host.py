@@ -39,7 +39,7 @@ def test_refuses_other_build(tmp_path):
     d = str(tmp_path / "ck")
     X = torch.from_numpy(np.arange(64 * 8, dtype=np.float32).reshape(64, 8))
     p = K.Params(n=64, d=8, k=4, T=2, leaf_max=16, rounds=1, seed=5)
-    # the directory takes this build's parameters and digest, then the host tensor is refused
+    # the directory records these parameters and the data's digest, then the host tensor is refused
     with pytest.raises(ValueError, match="device tensor"):
         C.build_resumable(X, p, d)
     assert os.path.exists(os.path.join(d, "meta.json"))

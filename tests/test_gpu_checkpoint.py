@@ -64,7 +64,7 @@ def test_resume_from_every_stage(dev, tmp_path, case):
     assert _same(ref, (out[0].cpu().numpy(), out[1].cpu().numpy()))
     s = C.checkpoint_stages(ck)
     assert s == {"divisions": list(range(T)), "perms": [], "merged": True, "rounds": rounds}
-    # resume after round 1
+    # resume after the first propagation round
     _rm(ck, f"round_{rounds}_ids.npy", f"round_{rounds}_dist.npy")
     assert _same(ref, [t.cpu().numpy() for t in C.build_resumable(X_t, p, ck)])
     # resume from the merged lists
