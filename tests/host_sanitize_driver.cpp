@@ -141,6 +141,41 @@ static void workspaces() {
   CHECK(knng_workspace_bytes(&q, KNNG_OP_LEAF) == 0);
 }
 
+// Seeded random parameter sets: whatever the planner and the layouts accept
+// must give trees with the invariants above and nonzero workspace sizes;
+// whatever they refuse must be refused with a message.
+static void random_params() {
+  uint64_t x = 0x9E3779B97F4A7C15ull;
+  auto next = [&x](uint64_t m) {   // xorshift64*, uniform enough for a sweep
+    x ^= x >> 12;
+    x ^= x << 25;
+    x ^= x >> 27;
+    return (x * 0x2545F4914F6CDD1Dull) % m;
+  };
+  for (int it = 0; it < 400; ++it) {
+    knng_params p = base(1 + (int64_t)next(it % 10 == 0 ? 4000000 : 50000), 4 * (1 + (int)next(64)),
+                         1 + (int)next(64));
+    p.T = 1 + (int)next(24);
+    p.leaf_max = 2 + (int)next(it % 3 == 0 ? 4000 : 600);
+    p.leaf_cap_cycle = next(2) ? 3 : 0;
+    p.q_lo_pm = 1 + (int)next(998);
+    p.q_hi_pm = p.q_lo_pm + (int)next(999 - p.q_lo_pm);
+    p.seed = next(1ull << 40);
+    p.split = (int)next(2);
+    p.precision = (int)next(2);
+    p.rerank_m = (int)next(20);
+    p.visit_max = next(3) == 0 ? (int)next(200) : 0;
+    p.rate_permille = next(4) == 0 ? (int)next(200) : 0;
+    p.metric = (int)next(2);
+    p.rounds = (int)next(4);
+    check_shape(p, (int)next(64));
+    for (int op = KNNG_OP_DIVIDE; op <= KNNG_OP_COLEAF; ++op) {
+      const size_t b = knng_workspace_bytes(&p, op);
+      if (b == 0 && op != KNNG_OP_MERGE) CHECK(std::strlen(knng_last_error()) > 0);
+    }
+  }
+}
+
 // Device entry points stop on the host: null or misaligned arguments, or a
 // workspace too small, before any HIP call.  The host buffers stand in for
 // device memory and are never dereferenced.
@@ -218,6 +253,7 @@ int main(int argc, char** argv) {
   if (all) {
     shapes();
     workspaces();
+    random_params();
     rejected_calls();
     tuning_and_fault();
   }
