@@ -865,6 +865,184 @@ __global__ __launch_bounds__(DIV_THREADS) void k_pca_dirs(DivideLevelArgs a) {
   for (int j = threadIdx.x; j < d; j += DIV_THREADS) a.pca_dirs[(size_t)sd.dir_index * d + j] = sg * v[j];
 }
 
+// Principal direction for PCA_LDS_DMAX < d <= PCA_ROWS_DMAX, one pass over
+// the sample per iteration: w = Y^T (Y v) is the sum over sample rows of
+// (y_i - mu) t_i with t_i = (y_i - mu) . v, so a wave that holds a whole
+// row (lane l: float4 chunks l, l + 64, ... of it; NC4 of them) forms t_i by
+// a wave sum and adds the row times t_i into its own partial of w in
+// registers.  Waves take rows w, w + 4, ...; their partials are added in
+// wave order.  Every wave keeps the whole of v and mu, so only the partials
+// of w and the mean cross waves (through LDS).  Same sample, start vector,
+// iteration count and sign rule as k_pca_lds; the sums run in another
+// order.  The sample is read once per iteration (coalesced rows, four in
+// flight per wave) instead of twice.
+constexpr int PCA_ROWS_DMAX = 1024;
+
+__device__ __forceinline__ float wave_sum_f(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;   // the same value in every lane (each step adds a pair in both orders)
+}
+
+template <int NC4>
+__global__ __launch_bounds__(DIV_THREADS) void k_pca_rows(DivideLevelArgs a) {
+  if (a.skip && *a.skip) return;   // uniform: a later division of a stopped build
+  constexpr int NW = DIV_THREADS / 64;
+  constexpr int RU = 4;            // rows in flight per wave
+  __shared__ uint32_t rows[256];
+  __shared__ float4 part[NW][64 * NC4];
+  const SegDesc sd = a.segs[blockIdx.x];
+  const int d = a.d, c4 = d >> 2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t m = sd.m;
+  const uint32_t s = m < 256 ? m : 256;
+  uint32_t wd = m / s;
+  if (wd < 1) wd = 1;
+  if (threadIdx.x < s) {
+    uint32_t pos = (uint32_t)(((uint64_t)threadIdx.x * m) / s) +
+                   (uint32_t)(rand64(a.seed, TAG_SAMPLE, sd.t, sd.v, threadIdx.x) % wd);
+    rows[threadIdx.x] = a.perm_in[(size_t)sd.slot * (size_t)a.n + sd.off + pos];
+  }
+  bool ok[NC4];
+  float4 v[NC4];
+#pragma unroll
+  for (int c = 0; c < NC4; ++c) {
+    const int q = lane + 64 * c;   // this lane's float4 chunk c: columns 4q .. 4q + 3
+    ok[c] = q < c4;
+    v[c] = ok[c] ? make_float4(rp_entry(a.seed, sd.t, sd.v, 4 * q), rp_entry(a.seed, sd.t, sd.v, 4 * q + 1),
+                               rp_entry(a.seed, sd.t, sd.v, 4 * q + 2), rp_entry(a.seed, sd.t, sd.v, 4 * q + 3))
+                 : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  __syncthreads();
+  // the rows of this wave, RU at a time; rows past the sample load row 0
+  // and are not used
+  auto load_rows = [&](uint32_t i0, float4 (&y)[RU][NC4]) {
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const uint32_t i = i0 + (uint32_t)(NW * u);
+      const float4* yr = reinterpret_cast<const float4*>(a.X + (size_t)rows[i < s ? i : 0] * d);
+#pragma unroll
+      for (int c = 0; c < NC4; ++c) y[u][c] = ok[c] ? yr[lane + 64 * c] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto add4 = [](float4& r, const float4 x) { r.x += x.x; r.y += x.y; r.z += x.z; r.w += x.w; };
+  // partials of the waves added in wave order into every wave's registers
+  auto gather = [&](float4 (&acc)[NC4], float4 (&out)[NC4]) {
+#pragma unroll
+    for (int c = 0; c < NC4; ++c) part[wv][lane + 64 * c] = acc[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC4; ++c) {
+      float4 r = part[0][lane + 64 * c];
+#pragma unroll
+      for (int w2 = 1; w2 < NW; ++w2) add4(r, part[w2][lane + 64 * c]);
+      out[c] = r;
+    }
+    __syncthreads();   // part is written again by the next gather
+  };
+  // mean
+  float4 mu[NC4];
+  {
+    float4 acc[NC4];
+#pragma unroll
+    for (int c = 0; c < NC4; ++c) acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (uint32_t i0 = wv; i0 < s; i0 += NW * RU) {
+      float4 y[RU][NC4];
+      load_rows(i0, y);
+#pragma unroll
+      for (int u = 0; u < RU; ++u)
+        if (i0 + (uint32_t)(NW * u) < s) {
+#pragma unroll
+          for (int c = 0; c < NC4; ++c) add4(acc[c], y[u][c]);
+        }
+    }
+    gather(acc, mu);
+    const float fs = (float)s;
+#pragma unroll
+    for (int c = 0; c < NC4; ++c) mu[c] = make_float4(mu[c].x / fs, mu[c].y / fs, mu[c].z / fs, mu[c].w / fs);
+  }
+  auto dot4 = [](const float4 x, const float4 y, float acc) {
+    acc = __builtin_fmaf(x.x, y.x, acc);
+    acc = __builtin_fmaf(x.y, y.y, acc);
+    acc = __builtin_fmaf(x.z, y.z, acc);
+    return __builtin_fmaf(x.w, y.w, acc);
+  };
+  // normalise the start vector (every wave holds all of it)
+  {
+    float nn = 0.f;
+#pragma unroll
+    for (int c = 0; c < NC4; ++c) nn = dot4(v[c], v[c], nn);
+    nn = wave_sum_f(nn);
+    const float inv = nn > 0.f ? 1.0f / sqrtf(nn) : 0.f;
+#pragma unroll
+    for (int c = 0; c < NC4; ++c) v[c] = make_float4(v[c].x * inv, v[c].y * inv, v[c].z * inv, v[c].w * inv);
+  }
+  for (int itr = 0; itr < a.pca_iters; ++itr) {
+    float4 acc[NC4];
+#pragma unroll
+    for (int c = 0; c < NC4; ++c) acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (uint32_t i0 = wv; i0 < s; i0 += NW * RU) {
+      float4 y[RU][NC4];
+      load_rows(i0, y);
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        if (i0 + (uint32_t)(NW * u) >= s) break;   // uniform
+        float t = 0.f;
+#pragma unroll
+        for (int c = 0; c < NC4; ++c) {
+          float4& yc = y[u][c];
+          yc.x -= mu[c].x; yc.y -= mu[c].y; yc.z -= mu[c].z; yc.w -= mu[c].w;   // padded chunks stay 0
+          t = dot4(yc, v[c], t);
+        }
+        t = wave_sum_f(t);
+#pragma unroll
+        for (int c = 0; c < NC4; ++c) {
+          acc[c].x = __builtin_fmaf(y[u][c].x, t, acc[c].x);
+          acc[c].y = __builtin_fmaf(y[u][c].y, t, acc[c].y);
+          acc[c].z = __builtin_fmaf(y[u][c].z, t, acc[c].z);
+          acc[c].w = __builtin_fmaf(y[u][c].w, t, acc[c].w);
+        }
+      }
+    }
+    float4 w4[NC4];
+    gather(acc, w4);
+    float sq = 0.f;
+#pragma unroll
+    for (int c = 0; c < NC4; ++c) sq = dot4(w4[c], w4[c], sq);
+    sq = wave_sum_f(sq);
+    if (sq > 0.f) {
+      const float iv = 1.0f / sqrtf(sq);
+#pragma unroll
+      for (int c = 0; c < NC4; ++c) v[c] = make_float4(w4[c].x * iv, w4[c].y * iv, w4[c].z * iv, w4[c].w * iv);
+    }
+  }
+  // sign: the largest-magnitude entry positive, lowest index on ties (every
+  // wave holds v; wave 0 decides and writes)
+  if (wv != 0) return;
+  float best = -1.f;
+  int bj = 0x7FFFFFFF;
+  float bv = 0.f;
+#pragma unroll
+  for (int c = 0; c < NC4; ++c) {
+    const int j0 = 4 * (lane + 64 * c);
+    const float e[4] = {v[c].x, v[c].y, v[c].z, v[c].w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (ok[c] && fabsf(e[u]) > best) { best = fabsf(e[u]); bj = j0 + u; bv = e[u]; }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const float ob = __shfl_xor(best, o);
+    const int oj = __shfl_xor(bj, o);
+    const float ov = __shfl_xor(bv, o);
+    if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; bv = ov; }
+  }
+  const float sg = bv < 0.f ? -1.f : 1.f;
+  float4* out = reinterpret_cast<float4*>(a.pca_dirs + (size_t)sd.dir_index * d);
+#pragma unroll
+  for (int c = 0; c < NC4; ++c)
+    if (ok[c]) out[lane + 64 * c] = make_float4(sg * v[c].x, sg * v[c].y, sg * v[c].z, sg * v[c].w);
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t value, size_t count) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -926,6 +1104,12 @@ hipError_t launch_divide_level(const DivideLevelArgs& a, hipStream_t s) {
       hipLaunchKernelGGL(k_pca_lds<false>, grid(shm), dim3(DIV_THREADS), shm, s, a);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       if (a.X8) hipLaunchKernelGGL(k_pca_lds<true>, grid(shm8), dim3(DIV_THREADS), shm8, s, a);
+    } else if (a.d <= PCA_ROWS_DMAX) {
+      const int nc4 = (a.d / 4 + 63) / 64;
+      if (nc4 == 1) hipLaunchKernelGGL(k_pca_rows<1>, dim3(a.n_segs), dim3(DIV_THREADS), 0, s, a);
+      else if (nc4 == 2) hipLaunchKernelGGL(k_pca_rows<2>, dim3(a.n_segs), dim3(DIV_THREADS), 0, s, a);
+      else if (nc4 == 3) hipLaunchKernelGGL(k_pca_rows<3>, dim3(a.n_segs), dim3(DIV_THREADS), 0, s, a);
+      else hipLaunchKernelGGL(k_pca_rows<4>, dim3(a.n_segs), dim3(DIV_THREADS), 0, s, a);
     } else {
       hipLaunchKernelGGL(k_pca_dirs, dim3(a.n_segs), dim3(DIV_THREADS), base, s, a);
     }

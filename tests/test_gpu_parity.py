@@ -128,7 +128,12 @@ def test_divide_direction_override(dev):
 
 
 @pytest.mark.parametrize("case", [("gauss", 20_000, 32, 256, 16), ("sift", 20_000, 128, 512, 16),
-                                  ("gist", 3_000, 960, 256, 8), ("gauss", 700, 8, 16, 30)],
+                                  ("gist", 3_000, 960, 256, 8), ("gauss", 700, 8, 16, 30),
+                                  # one-pass large-d kernel: 1, 2, 3 and 4 float4 chunks per lane,
+                                  # ragged last chunk, then past its limit (d > 1024)
+                                  ("gauss", 3_000, 140, 256, 16), ("gist", 2_000, 400, 256, 16),
+                                  ("gauss", 2_000, 720, 128, 16), ("gist", 2_000, 1024, 256, 8),
+                                  ("gauss", 1_500, 1028, 256, 8)],
                          ids=lambda c: f"{c[0]}-n{c[1]}-d{c[2]}-it{c[4]}")
 def test_pca_divide(dev, case):
     """Principal-direction split (Section 3.4): wherever the GPU tree and the
