@@ -44,19 +44,23 @@ def _rm(d, *names):
 
 
 CASES = [
-    # name, data, n, d, k, T, leaf_max, rounds, split, metric, visit_max
-    ("sift-rp", "sift", 20_000, 128, 10, 3, 512, 2, K.SPLIT_RP, K.METRIC_L2, 0),
-    ("gauss-pca-cos", "gauss", 6_000, 32, 8, 3, 128, 2, K.SPLIT_PCA, K.METRIC_COSINE, 0),
-    ("gauss-bestfirst", "gauss", 6_000, 16, 10, 2, 128, 2, K.SPLIT_RP, K.METRIC_L2, 40),
+    # name, data, n, d, k, T, leaf_max, rounds, split, metric, visit_max, other parameters
+    ("sift-rp", "sift", 20_000, 128, 10, 3, 512, 2, K.SPLIT_RP, K.METRIC_L2, 0, {}),
+    ("gauss-pca-cos", "gauss", 6_000, 32, 8, 3, 128, 2, K.SPLIT_PCA, K.METRIC_COSINE, 0, {}),
+    ("gauss-bestfirst", "gauss", 6_000, 16, 10, 2, 128, 2, K.SPLIT_RP, K.METRIC_L2, 40, {}),
+    # BF16 Gram with re-rank, uneven splits and caps cycling up to 2 leaf_max
+    ("sift-bf16-uneven", "sift", 20_000, 128, 10, 3, 512, 1, K.SPLIT_PCA, K.METRIC_L2, 0,
+     dict(precision=K.BF16, rerank_m=16, leaf_cap_cycle=3, q_lo_pm=300, q_hi_pm=700)),
 ]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_resume_from_every_stage(dev, tmp_path, case):
-    name, kind, n, d, k, T, g, rounds, split, metric, visit = case
+    name, kind, n, d, k, T, g, rounds, split, metric, visit, extra = case
     say("resume", name)
     X = datagen.sift_like(n, d, 40, 301) if kind == "sift" else datagen.gaussian_mixture(n, d, 12, 302)
-    p = K.Params(n=n, d=d, k=k, T=T, leaf_max=g, rounds=rounds, split=split, metric=metric, visit_max=visit, seed=303)
+    p = K.Params(n=n, d=d, k=k, T=T, leaf_max=g, rounds=rounds, split=split, metric=metric, visit_max=visit, seed=303,
+                 **extra)
     X_t = torch.from_numpy(X).to(dev)
     ref = _whole(X_t, p)
     ck = str(tmp_path / "ck")
