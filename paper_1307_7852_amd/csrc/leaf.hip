@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_exact_check(const float* __restrict__ X
 
 // One leaf: members perm[off .. off+m), rows written to ids/dist (already
 // offset to the leaf's division).  `key` names the leaf in the fallback list.
-template <int KC, int KP, bool BF16, int W, int KT>
+template <int KC, int KP, bool BF16, int W, int KT, bool PAIR>
 __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, BF16, W>& S, const uint32_t* __restrict__ perm,
                                           uint32_t* __restrict__ ids_out, float* __restrict__ dist_out, int64_t off,
                                           int m, uint32_t key) {
@@ -350,6 +350,26 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
   // st < 2^32 / nchunk, far above any step count here
   const uint32_t nch_m = nchunk == 1 ? 0u : (uint32_t)((0x100000000ull + (uint64_t)nchunk - 1u) / (uint64_t)nchunk);
   auto step_tile = [&](int st) -> int { return nchunk == 1 ? st : (int)__umulhi((uint32_t)st, nch_m); };
+  // PAIR (rows of several chunks): tiles go in pairs, chunk by chunk --
+  // (tile 2p, chunk c), (tile 2p + 1, chunk c), (2p, c + 1), ... -- so one
+  // load of a wave's query fragment of chunk c serves both tiles, while the
+  // pair's other partial Gram waits in a second accumulator; an odd last
+  // tile goes alone.  Each tile still takes its chunks in increasing order.
+  const bool pair = PAIR && nchunk > 1;                      // uniform
+  const int full = pair ? (ntile >> 1) * 2 * nchunk : 0;     // steps of whole pairs
+  auto step_tc = [&](int st, int& tile, int& kci) {
+    if (!pair) {
+      tile = step_tile(st);
+      kci = st - tile * nchunk;
+    } else if (st < full) {
+      const int pr = st / (2 * nchunk), r = st - pr * 2 * nchunk;
+      tile = 2 * pr + (r & 1);
+      kci = r >> 1;
+    } else {
+      tile = ntile - 1;
+      kci = st - full;
+    }
+  };
 
   // Integer keys straight from the Gram (integer data, exact in the Gram's
   // input type, one chunk, leaves of at most 512; in BF16 such leaves are
@@ -384,8 +404,9 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
   // around it), which a d that is a multiple of KC never needs.
   const bool dfull = d % KC == 0 && TILE_F4 % C::THREADS == 0;   // uniform
   auto stage_load = [&](int st, float4 (&rg)[STAGE_F4]) {
-    const int t = step_tile(st);
-    int c0 = t * TILE, kc = (st - t * nchunk) * KC;
+    int t, kci;
+    step_tc(st, t, kci);
+    const int c0 = t * TILE, kc = kci * KC;
 #pragma unroll
     for (int u = 0; u < STAGE_F4; ++u) {
       int e = tid + u * C::THREADS;
@@ -403,8 +424,9 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
   // member norms (rows of a tile are held by F4_PER_ROW consecutive lanes,
   // reduced by shuffles)
   auto stage_store = [&](int st, int buf, const float4 (&rg)[STAGE_F4], bool norms) {
-    const int t = step_tile(st);
-    int c0 = t * TILE, kci = st - t * nchunk, kc = kci * KC;
+    int t, kci;
+    step_tc(st, t, kci);
+    const int c0 = t * TILE, kc = kci * KC;
 #pragma unroll
     for (int u = 0; u < STAGE_F4; ++u) {
       int e = tid + u * C::THREADS;
@@ -530,6 +552,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
 #pragma unroll
     for (int j = 0; j < KP; ++j) Lk[j] = __uint_as_float(KEY_NONE);
     f32x16 acc0 = {0};
+    f32x16 acc_o = {0};   // PAIR: the other tile's partial Gram
     if (!staged) {
       for (int s0 = 0; s0 < 2 && s0 < nsteps; ++s0) {
         float4 rg[STAGE_F4];
@@ -541,11 +564,13 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
     __syncthreads();
     for (int st = 0; st < nsteps; ++st) {
       const int buf = (st + bufbase) & (TILE_BUFS - 1);
-      const int tl = step_tile(st);
-      const int c0 = tl * TILE, kci = st - tl * nchunk;
+      int tl, kci;
+      step_tc(st, tl, kci);
+      const int c0 = tl * TILE;
       // the query chunk is loaded before the next tile's prefetch so that the
       // MFMAs wait only for the older loads and the prefetch stays in flight
-      if (wave_on && nchunk > 1) qf.load(qrow, kci * KC, d, h, S.mu, qok);
+      // (in a pair, by its first tile only)
+      if (wave_on && nchunk > 1 && !(pair && st < full && (st & 1))) qf.load(qrow, kci * KC, d, h, S.mu, qok);
       float4 rg[STAGE_F4];
       // step st stages step st + 2 of this pass, or of the next pass over
       // the leaf, or else re-stages its own tile into a buffer nobody reads
@@ -694,6 +719,13 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
             else if (kt <= KP / 2 + KP / 8) insert(std::integral_constant<int, KP / 2 + KP / 8>{});
             else if (kt <= KP - KP / 4) insert(std::integral_constant<int, KP - KP / 4>{});
             else insert(std::integral_constant<int, KP>{});
+          }
+        }
+        if constexpr (PAIR) {
+          if (pair && st < full) {   // uniform: hand over to the pair's other tile
+            const f32x16 tmp = acc0;
+            acc0 = acc_o;
+            acc_o = tmp;
           }
         }
       }
@@ -872,7 +904,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a, LeafShared<KC, KP, 
 // Single-division mode: one workgroup per leaf.  Batched mode: a persistent
 // grid; each workgroup takes the next leaf from the work list (largest
 // first) until the list is exhausted, so every workgroup reaches the exit.
-template <int KC, int KP, bool BF16, int W, int KT>
+template <int KC, int KP, bool BF16, int W, int KT, bool PAIR>
 __global__ __launch_bounds__((Cfg<KP, W>::THREADS)) void k_leaf(LeafArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   using Sh = LeafShared<KC, KP, BF16, W>;
@@ -913,7 +945,7 @@ __global__ __launch_bounds__((Cfg<KP, W>::THREADS)) void k_leaf(LeafArgs a) {
       off = a.leaf_off[idx];
       m = (int)(a.leaf_off[idx + 1] - off);
     }
-    leaf_body<KC, KP, BF16, W, KT>(a, S, perm, ids_out, dist_out, off, m, idx);
+    leaf_body<KC, KP, BF16, W, KT, PAIR>(a, S, perm, ids_out, dist_out, off, m, idx);
     if (m > 0) rows += (unsigned long long)m;
     if (a.work && threadIdx.x == 0) next = following;
     __syncthreads();
@@ -1000,14 +1032,14 @@ __global__ __launch_bounds__(256) void k_leaf_exact(LeafArgs a) {
   }
 }
 
-template <int KC, int KP, bool BF16, int W, int KT>
+template <int KC, int KP, bool BF16, int W, int KT, bool PAIR = false>
 hipError_t launch_leaf_t(const LeafArgs& a, hipStream_t s) {
   using Sh = LeafShared<KC, KP, BF16, W>;
   if constexpr (sizeof(Sh) + 64 > 160 * 1024) {
     return hipErrorInvalidConfiguration;   // this tile shape does not fit a CU's LDS
   } else {
     size_t shm = sizeof(Sh);
-    auto kern = k_leaf<KC, KP, BF16, W, KT>;
+    auto kern = k_leaf<KC, KP, BF16, W, KT, PAIR>;
     constexpr int THREADS = Cfg<KP, W>::THREADS;
     static int per_cu = 0;
     if (per_cu == 0) {
@@ -1035,6 +1067,9 @@ template <int KC, int KP, bool BF16>
 hipError_t launch_leaf_w(const LeafArgs& a, hipStream_t s) {
   const int w = a.waves ? a.waves : (KP <= 32 ? 8 : 4);
   if (w == 8) {
+    // rows of more than one chunk: tiles in pairs (one query fragment load
+    // serves two tiles)
+    if (a.d > KC) return launch_leaf_t<KC, KP, BF16, 8, 0, true>(a, s);
     // the common shape (d in (64, 128], k + rerank_m <= 16, 8 waves) has an
     // instance per list-length tier, so its steps hold one insertion
     if constexpr (KC == 128 && KP == 16) {
